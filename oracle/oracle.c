@@ -313,8 +313,9 @@ static int32_t sat16(int32_t x)
  * Magnitude rule for the outgoing message, from the raw minimum m (0..127):
  *   wq == 0 : offset min-sum, max(m - offset, 0)
  *   wq >  0 : normalised min-sum with weight wq/16, min(127, (wq*m + 8) >> 4)
- * wq_table (nullable, [max_iter][Mb][Nb]) overrides the scalar wq per
- * iteration, block row and block column.
+ * wq_table (nullable, [max_iter][Mb][Nb]) replaces the scalar wq per
+ * iteration, block row and block column; its entries are always weights
+ * (an entry of 0 gives magnitude 0) and the offset is then unused.
  */
 int orc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
                   int offset, int wq, const uint8_t *wq_table, int early_term,
@@ -368,8 +369,10 @@ int orc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, 
                                 neg ^= 1;
                         }
                         int32_t mag;
+                        /* a table entry is always a weight (0 is weight 0);
+                         * only the scalar wq == 0 selects offset min-sum */
                         int wk = wq_table ? wq_table[((long)(k - 1) * Mb + i) * Nb + ly.col[i * Nb + e]] : wq;
-                        if (wk > 0) {
+                        if (wq_table || wk > 0) {
                             mag = (wk * m + 8) >> 4;
                             if (mag > 127)
                                 mag = 127;

@@ -85,6 +85,24 @@ def test_single_check_int(mode):
         assert np.array_equal(post[f], q + sign * mag), f
 
 
+def test_single_check_int_weight_table():
+    # A weight table holds 1/16-step weights per (iteration, block row,
+    # block column); an entry of 0 is weight 0 (no message), never the
+    # offset rule, and the offset argument is unused.
+    d = 6
+    rng = np.random.default_rng(8)
+    llr = rng.integers(-127, 128, (100, d)).astype(np.int8)
+    h = np.zeros((1, d), np.int16)
+    wt = np.array([[[0, 3, 16, 31, 12, 7]]], np.uint8)
+    _, post, _, _ = oracle.decode_i8(h, 1, llr, max_iter=1, offset=5, wq=0, wq_table=wt, early_term=False)
+    for f in range(100):
+        q = llr[f].astype(np.int64)
+        sign, m = _check_node_sorted(q, lambda m: np.minimum(m, 127))
+        mag = np.minimum(127, (wt[0, 0].astype(np.int64) * m + 8) >> 4)
+        assert np.array_equal(post[f], q + sign * mag), f
+    assert (post[:, 0] == llr[:, 0]).all()
+
+
 @pytest.mark.parametrize("rate", list(synth.WIFI_RATES))
 def test_noiseless_one_iteration(rate):
     h = synth.wifi_code(rate, 27)
