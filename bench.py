@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Decoder throughput benchmark on one MI355X.
+
+Workload: the Wi-Fi-shaped Z = 81 (N = 1944) codes at all four rates
+(1/2, 2/3, 3/4, 5/6), 2^16 frames per launch, BPSK/AWGN frames at
+Eb/N0 = 2 dB generated and encoded on the GPU before timing. One step decodes
+every rate's batch twice -- FP32 normalised min-sum (alpha = 0.75) and the
+saturating int8/int16 offset min-sum (offset 1) -- at a fixed 10 iterations
+with early termination off, as the paper times its decoders. The reported
+value is decoded information bits per second over the whole step.
+
+Prints one JSON line. `--gpus` above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "decoded info Gbit/s at 10 iters (FP32, int8); learned vs plain NMS FER=1e-3 Eb/N0"
+Z = 81
+ITERS = 10
+EBN0_DB = 2.0
+ALPHA = 0.75
+OFFSET = 1
+SEED = 2024
+# Per edge and iteration the single-scan layered update needs: rebuild the
+# old message (magnitude select, sign), Q = L - R_old, the running
+# (min1, min2, argmin) update (three ops), the sign bit, the new message
+# (magnitude select, sign) and L = Q + R: 10 VALU operations.
+ALG_OPS_PER_EDGE_ITER = 10
+# Non-packed 32-bit VALU issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=1 << 16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=1024,
+                    help="frames per rate and path in the CPU-oracle baseline sample")
+    return ap.parse_args()
+
+
+def source_sha(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2306_12063_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, sha):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec or rec.get("source_sha") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cases, nframes):
+    """Times the CPU oracle on the first `nframes` frames of every (rate, path)
+    case, split over host threads (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    bits = 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for c in cases:
+            chunks = np.array_split(np.arange(nframes), threads)
+            if c["path"] == "f32":
+                fn = lambda ix, c=c: oracle.decode_f32(c["hbm"], Z, c["llr_host"][ix], max_iter=ITERS,
+                                                       alpha=ALPHA, early_term=False)
+            else:
+                fn = lambda ix, c=c: oracle.decode_i8(c["hbm"], Z, c["q_host"][ix], max_iter=ITERS,
+                                                      offset=OFFSET, early_term=False)
+            list(ex.map(fn, [ix for ix in chunks if len(ix)]))
+            bits += nframes * c["K"]
+    dt = time.perf_counter() - t0
+    return {"value": bits / dt / 1e9, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nframes} frames per rate and path (FP32 and int8, 4 rates, Z=81), "
+                      f"{ITERS} fixed iterations, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(frames are independent, so a multi-GPU run would split the batch; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2306_12063_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    F = args.frames
+    cases = []
+    for rate in synth.WIFI_RATES:
+        h = synth.wifi_code(rate, Z)
+        info = P.ldpc_code_info(h, Z)
+        N, K, E = info["N"], info["K"], info["E"]
+        s2 = synth.sigma2_from_ebn0(EBN0_DB, K / N)
+        bits_in = P.ldpc_random_bits(SEED, F, K, device=dev)
+        cw = P.ldpc_encode(h, Z, bits_in)
+        llr = P.ldpc_awgn_llr(SEED + 1, cw, float(np.sqrt(s2)), 2.0 / s2)
+        q = P.ldpc_quantize_i8(llr)
+        del bits_in, cw
+        for path in ("f32", "i8"):
+            cases.append(dict(rate=rate, path=path, hbm=h, N=N, K=K, E=E, llr=llr, q=q,
+                              bits=torch.empty((F, N), dtype=torch.uint8, device=dev),
+                              iters=torch.empty(F, dtype=torch.int32, device=dev),
+                              ok=torch.empty(F, dtype=torch.uint8, device=dev)))
+    torch.cuda.synchronize()
+
+    def launch(c):
+        if c["path"] == "f32":
+            P.ldpc_decode_f32(c["hbm"], Z, c["llr"], max_iter=ITERS, alpha=ALPHA, early_term=False,
+                              bits=c["bits"], iters=c["iters"], ok=c["ok"], want_post=False)
+        else:
+            P.ldpc_decode_i8(c["hbm"], Z, c["q"], max_iter=ITERS, offset=OFFSET, early_term=False,
+                             bits=c["bits"], iters=c["iters"], ok=c["ok"], want_post=False)
+
+    for _ in range(args.warmup):
+        for c in cases:
+            launch(c)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for j, c in enumerate(cases):
+            ev[s][j][0].record(stream)
+            launch(c)
+            ev[s][j][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    info_bits = args.steps * sum(F * c["K"] for c in cases)
+    value = info_bits / wall / 1e9
+    per = []
+    for j, c in enumerate(cases):
+        ms = float(np.mean([ev[s][j][0].elapsed_time(ev[s][j][1]) for s in range(args.steps)]))
+        ops = ALG_OPS_PER_EDGE_ITER * c["E"] * ITERS * F
+        in_b = c["N"] * (4 if c["path"] == "f32" else 1)
+        hbm_b = F * (in_b + c["N"] + 4 + 1)          # LLRs in; bits, iterations, ok out
+        per.append(dict(kernel=f"decode_{c['path']}", rate=c["rate"], ms=ms,
+                        gbit_s=F * c["K"] / (ms / 1e3) / 1e9,
+                        valu_tops=ops / (ms / 1e3) / 1e12, hbm_gbs=hbm_b / (ms / 1e3) / 1e9,
+                        alg_ops=ops, hbm_bytes=hbm_b))
+    dom = max(per, key=lambda p: p["ms"])
+    sha = source_sha("decode_f32.hip" if dom["kernel"] == "decode_f32" else "decode_i8.hip", "decode_common.h")
+    roofline = {"bound": "alu", "achieved": round(dom["valu_tops"], 3), "peak": round(PEAK_VALU_TOPS, 1),
+                "unit": "TOP/s", "frac": round(dom["valu_tops"] / PEAK_VALU_TOPS, 4),
+                "traffic": measured_traffic(dom["kernel"], sha),
+                "kernel": f"{dom['kernel']} rate {dom['rate']}", "avg_ms": round(dom["ms"], 4),
+                "alg_ops_per_launch": dom["alg_ops"], "alg_hbm_bytes_per_launch": dom["hbm_bytes"],
+                "hbm_frac": round(dom["hbm_gbs"] / PEAK_HBM_GBS, 5)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+i8", "data": "synthetic",
+        "config": {"workload": f"Wi-Fi-shaped synthetic QC-LDPC codes, Z=81 (N=1944), rates 1/2 2/3 3/4 5/6; "
+                               f"{F} frames per rate at Eb/N0={EBN0_DB} dB; FP32 NMS alpha={ALPHA} and "
+                               f"int8 OMS offset={OFFSET}; {ITERS} fixed iterations, early termination off",
+                   "frames_per_launch": F, "iterations": ITERS, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "per_kernel": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()
+                        if k not in ("alg_ops", "hbm_bytes")} for p in per],
+    }
+    if not args.no_cpu_baseline:
+        nf = min(args.cpu_frames, F)
+        for c in cases:
+            c["llr_host"] = c["llr"][:nf].cpu().numpy()
+            c["q_host"] = c["q"][:nf].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(cases, nf)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

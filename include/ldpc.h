@@ -1,0 +1,155 @@
+/*
+ * ldpc.h -- C ABI of libldpc: QC-LDPC direct encoding and layered
+ * single-scan min-sum decoding on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Palenik & Szitkey, "High Throughput Open-Source
+ * Implementation of Wi-Fi 6 and WiMAX LDPC Encoder and Decoder":
+ *   - the code is given by its base (model) matrix H_bm and expansion factor
+ *     Z (Sec. 1, eq. 2);
+ *   - encoding maps K = K_b Z information bits to the systematic codeword
+ *     c = [s p] (eq. 1) by the direct encoder of Sec. 2 (eqs. 8-15);
+ *   - decoding maps channel LLRs (eq. 17, positive = bit 0) to hard bits
+ *     (eq. 21), posterior LLRs (eq. 20) and an iteration count, running the
+ *     layered single-scan min-sum of Sec. 4 (eqs. 18, 20, 22, 23) and
+ *     stopping when H x = 0 if early termination is enabled.
+ *
+ * Conventions shared by every entry point
+ *  - Base matrix: `hbm` is a HOST pointer to int16 [Mb][Nb], row-major.
+ *    -1 is a zero block; s in [0, Z-1] is the identity cyclically shifted by
+ *    s, where check row r of block row i reaches variable j*Z + (r+s) mod Z.
+ *    Nb > Mb; N = Nb*Z, K = (Nb-Mb)*Z, M = Mb*Z.
+ *  - Data: every other pointer is a DEVICE pointer, frame-major and
+ *    row-contiguous ([F][N] means frame f, position n at f*N + n). Bits are
+ *    one per byte (0/1). The caller owns every buffer; the library keeps no
+ *    reference after the call returns.
+ *  - Execution: calls enqueue work on `stream` (a hipStream_t; NULL is the
+ *    null stream) and return before it finishes. Outputs are valid once the
+ *    stream is synchronised. F = 0 is a no-op that returns LDPC_OK.
+ *  - Errors: every call returns an int status. Arguments are validated on
+ *    the host before anything is enqueued; on error nothing is enqueued and
+ *    ldpc_last_error() describes the problem. No exception crosses the ABI.
+ *  - Threads: calls may be made from several host threads; the per-thread
+ *    error string is thread-local.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes */
+#define LDPC_OK 0
+#define LDPC_EINVAL (-1)   /* null pointer, negative size, shift outside [-1, Z-1],
+                              Nb <= Mb, a check row of degree < 2, max_iter < 1 */
+#define LDPC_ESTRUCT (-2)  /* base matrix lacks the structure the direct encoder needs */
+#define LDPC_ERANGE (-3)   /* valid code, but beyond this library's kernel limits */
+#define LDPC_EDEVICE (-4)  /* a HIP runtime call failed */
+#define LDPC_ENOMEM (-5)   /* host or device allocation failed */
+
+/* Kernel limits (LDPC_ERANGE beyond these). */
+#define LDPC_MAX_MB 16     /* block rows */
+#define LDPC_MAX_NB 32     /* block columns */
+#define LDPC_MAX_DEG 26    /* non-zero blocks in one block row (check degree) */
+#define LDPC_MAX_Z 256     /* expansion factor */
+
+/*
+ * Describes a code without touching the GPU (Sec. 1). Fills out[8] with:
+ *   N, K, M, E (edges = ones of H), the largest check degree, the row y of
+ *   h_b used by the direct encoder (or -1 when the code is not directly
+ *   encodable, eqs. 3-7), Mb, Nb.
+ * Returns LDPC_OK or LDPC_EINVAL.
+ */
+int ldpc_code_info(const int16_t *hbm, int Mb, int Nb, int Z, int64_t out[8]);
+
+/*
+ * Direct encoder (Sec. 2, eqs. 12-15).
+ *   info : device u8 [F][K], bits 0/1 (only bit 0 of each byte is read)
+ *   cw   : device u8 [F][N], receives [info | v_0 .. v_{Mb-1}]
+ * Requires the dual-diagonal structure of eqs. 3-7: h_b (column K_b) has
+ * equal non-negative entries in rows 0 and Mb-1 and exactly one more in a
+ * row y in between; H_b2' is the zero-shift staircase. Otherwise
+ * LDPC_ESTRUCT.
+ */
+int ldpc_encode(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, uint8_t *cw, int64_t F,
+                void *stream);
+
+/*
+ * Layered normalised min-sum decoder in FP32 (Sec. 4, eqs. 18-23).
+ *   llr      : device f32 [F][N], channel LLRs (eq. 17), positive = bit 0
+ *   max_iter : >= 1 iterations (one iteration = one pass over all Mb layers)
+ *   alpha    : normalisation of the check messages, R = sgn * (alpha * min)
+ *   early_term : nonzero -> stop a frame after the first iteration whose
+ *              hard decisions satisfy H x = 0
+ *   w        : nullable device f32 [max_iter][Mb][Nb]; when given, message
+ *              leaving block column j of block row i in iteration t (0-based)
+ *              is sgn * (w[t][i][j] * min) and alpha is ignored
+ *   bits     : device u8 [F][N]  hard decisions x = [L <= 0] (eq. 21)
+ *   post     : nullable device f32 [F][N] posterior LLRs (eq. 20)
+ *   iters    : device i32 [F]    completed iterations (1..max_iter)
+ *   ok       : nullable device u8 [F]  1 iff H x = 0 for the returned bits
+ * Arithmetic is IEEE FP32 with round-to-nearest and no fused multiply-add.
+ */
+int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                    float alpha, int early_term, const float *w, uint8_t *bits, float *post, int32_t *iters,
+                    uint8_t *ok, void *stream);
+
+/*
+ * Saturating fixed-point layered min-sum: int8 channel LLRs, int8 check
+ * messages, int16 posteriors (the fixed-point decoder of Sec. 5, with
+ * saturation instead of wrap-around).
+ *   llr     : device i8 [F][N]  (see ldpc_quantize_i8)
+ *   offset  : offset min-sum beta in LSB, 0..127, used when wq == 0 and
+ *             wq_table == NULL: magnitude = max(min - offset, 0)
+ *   wq      : 0, or normalisation weight in 1/16 steps (1..31):
+ *             magnitude = min(127, (wq*min + 8) >> 4)
+ *   wq_table: nullable device u8 [max_iter][Mb][Nb] of 1/16-step weights
+ *             (0..31) that replaces wq per iteration, block row and column
+ *   post    : nullable device i16 [F][N]
+ * |Q| is clipped to 127 before the minimum; sums saturate at +-32767.
+ * Other arguments as for ldpc_decode_f32.
+ */
+int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                   int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits, int16_t *post,
+                   int32_t *iters, uint8_t *ok, void *stream);
+
+/*
+ * Seeded information bits from Philox4x32-10 (Salmon et al., SC'11):
+ * bit k of frame f is bit (k mod 32) of word (k/32 mod 4) of
+ * Philox(counter = {k/128, f, 0, 0}, key = {seed low, seed high}).
+ *   info : device u8 [F][K]
+ */
+int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream);
+
+/*
+ * BPSK over AWGN and the channel LLR (eqs. 16-17):
+ *   LLR = ((1 - 2x) + sigma * z) * scale, with scale = 2 / sigma^2 chosen by
+ * the caller, evaluated in FP32 without fused multiply-add. z is a standard
+ * normal from Box-Muller on Philox(counter = {n/4, f, 1, 0}, key = seed):
+ * words (2p, 2p+1) with p = (n mod 4)/2 give u = ((word >> 8) + 1/2) 2^-24,
+ * z = sqrt(-2 ln u_a) * (cos for even n, sin for odd n)(2 pi u_b).
+ *   cw  : device u8 [F][N] codeword bits,  llr : device f32 [F][N]
+ */
+int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale, float *llr,
+                  void *stream);
+
+/*
+ * int8 quantiser for channel LLRs: q = clamp(rint(scale * llr), -127, 127),
+ * rounding half to even. llr: device f32 [n], q: device i8 [n].
+ */
+int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *stream);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char *ldpc_last_error(void);
+
+/* Drops cached per-code device tables (safe to call at any time). */
+void ldpc_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

@@ -1,0 +1,213 @@
+"""Python binding of libldpc, the MI355X QC-LDPC encoder/decoder library.
+
+The functions below carry the names of the C entry points declared in
+include/ldpc.h and only marshal arguments: base matrices travel as host
+int16 arrays, data as torch tensors on the GPU (PyTorch provides device
+memory and the current stream), and every step runs in the library's HIP
+kernels. There is no CPU fallback: if libldpc.so is missing the import of a
+function fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+__all__ = [
+    "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
+    "ldpc_quantize_i8", "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "EXPORTS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldpc.so")
+
+LDPC_OK, LDPC_EINVAL, LDPC_ESTRUCT, LDPC_ERANGE, LDPC_EDEVICE, LDPC_ENOMEM = 0, -1, -2, -3, -4, -5
+
+_p, _i32, _i64, _u64, _f32 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_float
+# name -> (argtypes, restype); every entry point of include/ldpc.h
+EXPORTS = {
+    "ldpc_code_info": ([_p, _i32, _i32, _i32, _p], _i32),
+    "ldpc_encode": ([_p, _i32, _i32, _i32, _p, _p, _i64, _p], _i32),
+    "ldpc_decode_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, _p], _i32),
+    "ldpc_decode_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p], _i32),
+    "ldpc_random_bits": ([_u64, _i64, _i64, _p, _p], _i32),
+    "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p], _i32),
+    "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
+    "ldpc_last_error": ([], C.c_char_p),
+    "ldpc_cache_clear": ([], None),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, code, name, msg):
+        super().__init__(f"{name} failed with status {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Loads libldpc.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"libldpc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+            L = C.CDLL(LIB_PATH)
+            for name, (args, res) in EXPORTS.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = res
+            _lib = L
+    return _lib
+
+
+def ldpc_last_error() -> str:
+    return lib().ldpc_last_error().decode()
+
+
+def ldpc_cache_clear() -> None:
+    lib().ldpc_cache_clear()
+
+
+def _check(rc, name):
+    if rc != LDPC_OK:
+        raise LdpcError(rc, name, ldpc_last_error())
+
+
+def _hbm(hbm):
+    h = np.ascontiguousarray(np.asarray(hbm), dtype=np.int16)
+    if h.ndim != 2:
+        raise ValueError("base matrix must be 2-D [Mb][Nb]")
+    return h
+
+
+def _hptr(h):
+    return h.ctypes.data_as(C.c_void_p)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, name, shape=None):
+    """Checks a device tensor argument and returns its address."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _opt(t, dtype, name, shape=None):
+    return None if t is None else _dev(t, dtype, name, shape)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def ldpc_code_info(hbm, Z):
+    """Host-only description of a code: dict with N, K, M, E, dmax, enc_y."""
+    h = _hbm(hbm)
+    out = np.zeros(8, np.int64)
+    _check(lib().ldpc_code_info(_hptr(h), h.shape[0], h.shape[1], Z, out.ctypes.data_as(C.c_void_p)),
+           "ldpc_code_info")
+    return dict(N=int(out[0]), K=int(out[1]), M=int(out[2]), E=int(out[3]), dmax=int(out[4]),
+                enc_y=int(out[5]), Mb=int(out[6]), Nb=int(out[7]))
+
+
+def ldpc_encode(hbm, Z, info, cw=None, stream=None):
+    """Direct encoder: info u8 [F][K] (GPU) -> codewords u8 [F][N] (GPU)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F = info.shape[0]
+    K, N = (Nb - Mb) * Z, Nb * Z
+    ip = _dev(info, torch.uint8, "info", (F, K))
+    if cw is None:
+        cw = torch.empty((F, N), dtype=torch.uint8, device=info.device)
+    cp = _dev(cw, torch.uint8, "cw", (F, N))
+    _check(lib().ldpc_encode(_hptr(h), Mb, Nb, Z, ip, cp, F, _stream(stream)), "ldpc_encode")
+    return cw
+
+
+def ldpc_decode_f32(hbm, Z, llr, max_iter=10, alpha=0.75, early_term=True, w=None, bits=None, post=None,
+                    iters=None, ok=None, want_post=True, stream=None):
+    """FP32 layered min-sum. Returns (bits u8, post f32 or None, iters i32, ok u8)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    dev = llr.device
+    lp = _dev(llr, torch.float32, "llr", (F, Nb * Z))
+    wp = _opt(w, torch.float32, "w", (max_iter, Mb, Nb))
+    bits = torch.empty((F, N), dtype=torch.uint8, device=dev) if bits is None else bits
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.float32, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+    ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+    _check(lib().ldpc_decode_f32(_hptr(h), Mb, Nb, Z, lp, F, int(max_iter), float(alpha), int(bool(early_term)), wp,
+                                 _dev(bits, torch.uint8, "bits", (F, N)), _opt(post, torch.float32, "post", (F, N)),
+                                 _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)),
+                                 _stream(stream)), "ldpc_decode_f32")
+    return bits, post, iters, ok
+
+
+def ldpc_decode_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, wq_table=None, early_term=True, bits=None,
+                   post=None, iters=None, ok=None, want_post=True, stream=None):
+    """Saturating int8/int16 layered min-sum. Returns (bits u8, post i16 or None, iters i32, ok u8)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    dev = llr.device
+    lp = _dev(llr, torch.int8, "llr", (F, Nb * Z))
+    tp = _opt(wq_table, torch.uint8, "wq_table", (max_iter, Mb, Nb))
+    bits = torch.empty((F, N), dtype=torch.uint8, device=dev) if bits is None else bits
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.int16, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+    ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+    _check(lib().ldpc_decode_i8(_hptr(h), Mb, Nb, Z, lp, F, int(max_iter), int(offset), int(wq), tp,
+                                int(bool(early_term)), _dev(bits, torch.uint8, "bits", (F, N)),
+                                _opt(post, torch.int16, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
+                                _opt(ok, torch.uint8, "ok", (F,)), _stream(stream)), "ldpc_decode_i8")
+    return bits, post, iters, ok
+
+
+def ldpc_quantize_i8(llr, scale=4.0, out=None, stream=None):
+    torch = _torch()
+    out = torch.empty(llr.shape, dtype=torch.int8, device=llr.device) if out is None else out
+    _check(lib().ldpc_quantize_i8(_dev(llr, torch.float32, "llr"), _dev(out, torch.int8, "q", llr.shape),
+                                  llr.numel(), float(scale), _stream(stream)), "ldpc_quantize_i8")
+    return out
+
+
+def ldpc_random_bits(seed, F, K, out=None, device="cuda", stream=None):
+    torch = _torch()
+    out = torch.empty((F, K), dtype=torch.uint8, device=device) if out is None else out
+    _check(lib().ldpc_random_bits(int(seed), F, K, _dev(out, torch.uint8, "info", (F, K)), _stream(stream)),
+           "ldpc_random_bits")
+    return out
+
+
+def ldpc_awgn_llr(seed, cw, sigma, scale, out=None, stream=None):
+    torch = _torch()
+    F, N = cw.shape
+    out = torch.empty((F, N), dtype=torch.float32, device=cw.device) if out is None else out
+    _check(lib().ldpc_awgn_llr(int(seed), _dev(cw, torch.uint8, "cw", (F, N)), F, N, float(sigma), float(scale),
+                               _dev(out, torch.float32, "llr", (F, N)), _stream(stream)), "ldpc_awgn_llr")
+    return out

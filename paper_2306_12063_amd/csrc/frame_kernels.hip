@@ -1,0 +1,206 @@
+// Frame generation kernels for gfx950: seeded information bits, the direct
+// QC encoder (Sec. 2, eqs. 12-15), BPSK over AWGN with the channel LLR
+// (eqs. 16-17) and the int8 LLR quantiser.
+#include <math.h>
+
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies, a swap and a key xor; the key advances by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+// Bit k of frame f = bit (k % 32) of word (k / 32 % 4) of
+// Philox({k / 128, f, 0, 0}, seed). One thread per 128-bit block.
+__global__ void k_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *__restrict__ out)
+{
+    const int64_t blocks_per_frame = (K + 127) / 128;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= F * blocks_per_frame)
+        return;
+    const int64_t f = gid / blocks_per_frame, b = gid - f * blocks_per_frame;
+    const uint4 o = philox4x32_10(make_uint4((uint32_t)b, (uint32_t)f, 0u, 0u),
+                                  make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+    uint8_t *dst = out + f * K;
+    const int64_t k0 = b * 128;
+    for (int j = 0; j < 128 && k0 + j < K; ++j)
+        dst[k0 + j] = (uint8_t)((w[j >> 5] >> (j & 31)) & 1u);
+}
+
+// Noise sample n of frame f: Box-Muller on words (2p, 2p+1), p = (n%4)/2, of
+// Philox({n / 4, f, 1, 0}, seed), with u = ((word >> 8) + 1/2) 2^-24;
+// cos for even n, sin for odd n. LLR = ((1 - 2x) + sigma z) * scale, in FP32
+// without fused multiply-add. One thread per 4 consecutive positions.
+__global__ void k_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *__restrict__ cw, float sigma,
+                           float scale, float *__restrict__ llr)
+{
+    const int64_t quads = (N + 3) / 4;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= F * quads)
+        return;
+    const int64_t f = gid / quads, q = gid - f * quads;
+    const uint4 o = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)f, 1u, 0u),
+                                  make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+    const float two_pi = 6.28318530717958647692f;
+    const float inv24 = 1.0f / 16777216.0f;
+    const float ua0 = ((float)(o.x >> 8) + 0.5f) * inv24, ub0 = ((float)(o.y >> 8) + 0.5f) * inv24;
+    const float ua1 = ((float)(o.z >> 8) + 0.5f) * inv24, ub1 = ((float)(o.w >> 8) + 0.5f) * inv24;
+    const float r0 = sqrtf(-2.0f * logf(ua0)), r1 = sqrtf(-2.0f * logf(ua1));
+    const float z[4] = {r0 * cosf(two_pi * ub0), r0 * sinf(two_pi * ub0), r1 * cosf(two_pi * ub1),
+                        r1 * sinf(two_pi * ub1)};
+    const int64_t base = f * N + q * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (q * 4 + j < N) {
+            const float x = (cw[base + j] & 1u) ? -1.0f : 1.0f;
+            const float y = x + sigma * z[j];
+            llr[base + j] = y * scale;
+        }
+    }
+}
+
+__global__ void k_quantize_i8(const float *__restrict__ in, int8_t *__restrict__ out, int64_t n, float scale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float v = rintf(scale * in[i]);
+    v = fminf(fmaxf(v, -127.0f), 127.0f);
+    out[i] = (int8_t)v;
+}
+
+// Direct encoder. A workgroup encodes G frames; thread (g, r) owns row r of
+// every Z-bit block of frame g.
+//   S_i[r] = xor_j u_j[(r + H(i,j)) mod Z] over the information columns (eq. 15)
+//   T = xor_i S_i,  v_0[c] = T[(c - h_b(y)) mod Z]                  (eq. 12)
+//   v_1 = P_{h_b(0)} v_0 + S_0                                     (eq. 13)
+//   v_{i+1} = v_i + P_{h_b(i)} v_0 + S_i,  i = 1 .. Mb-2          (eq. 14)
+// The S_i bits of a thread live in one register; T and v_0 go through LDS
+// because v_0 is read at shifted rows.
+__global__ __launch_bounds__(kMaxThreads) void k_encode(const Sched sc, const int G, const uint8_t *__restrict__ info,
+                                                         uint8_t *__restrict__ cw, int64_t F)
+{
+    extern __shared__ uint8_t lds[];
+    const int Z = sc.Z, K = sc.K, N = sc.N, Mb = sc.Mb, Kb = sc.Nb - sc.Mb;
+    uint8_t *ubuf = lds;                        // [G][K]
+    uint8_t *tbuf = lds + (size_t)G * K;        // [G][Z]
+    uint8_t *v0buf = tbuf + (size_t)G * Z;      // [G][Z]
+    const int tid = threadIdx.x;
+    const int64_t f0 = (int64_t)blockIdx.x * G;
+    for (int g = 0; g < G; ++g) {
+        const int64_t f = f0 + g;
+        if (f >= F)
+            break;
+        for (int k = tid; k < K; k += blockDim.x) {
+            const uint8_t b = info[f * K + k] & 1u;
+            ubuf[g * K + k] = b;
+            cw[f * N + k] = b;
+        }
+    }
+    __syncthreads();
+    const int g = tid / Z, r = tid - (tid / Z) * Z;
+    const bool on = g < G && f0 + g < F;
+    uint32_t S = 0;
+    if (on) {
+        const uint8_t *u = ubuf + g * K;
+        for (int i = 0; i < Mb; ++i) {
+            uint32_t acc = 0;
+            const int d = sc.deg[i];
+            for (int e = 0; e < d; ++e) {
+                const uint32_t ew = sc.edge[i][e];
+                const int col = (int)(ew >> 16);
+                if (col >= Kb)
+                    break;     // edges are in ascending column: the rest are parity columns
+                int x = r + (int)(ew & 0xffffu);
+                x = x >= Z ? x - Z : x;
+                acc ^= u[col * Z + x];
+            }
+            S |= acc << i;
+        }
+        tbuf[g * Z + r] = (uint8_t)(__popc(S) & 1);
+    }
+    __syncthreads();
+    if (on) {
+        const int hy = sc.hb[sc.enc_y];
+        int c = r - hy;
+        c = c < 0 ? c + Z : c;
+        v0buf[g * Z + r] = tbuf[g * Z + c];
+    }
+    __syncthreads();
+    if (on) {
+        const uint8_t *v0 = v0buf + g * Z;
+        uint8_t *p = cw + (f0 + g) * N + K;
+        const uint8_t v0r = v0[r];
+        p[r] = v0r;
+        int h0 = r + sc.hb[0];
+        h0 = h0 >= Z ? h0 - Z : h0;
+        uint8_t v = v0[h0] ^ (uint8_t)(S & 1u);
+        p[Z + r] = v;
+        for (int i = 1; i <= Mb - 2; ++i) {
+            const int hi = sc.hb[i];
+            uint8_t t = v ^ (uint8_t)((S >> i) & 1u);
+            if (hi >= 0) {
+                int x = r + hi;
+                x = x >= Z ? x - Z : x;
+                t ^= v0[x];
+            }
+            v = t;
+            p[(i + 1) * Z + r] = v;
+        }
+    }
+}
+
+inline int grid_for(int64_t work, int threads) { return (int)((work + threads - 1) / threads); }
+
+}  // namespace
+
+int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_quantize_i8, dim3(grid_for(n, 256)), dim3(256), 0, stream, llr, q, n, scale);
+    return check_launch(__func__);
+}
+
+int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream)
+{
+    const int64_t work = F * ((K + 127) / 128);
+    hipLaunchKernelGGL(k_random_bits, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, F, K, info);
+    return check_launch(__func__);
+}
+
+int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale, float *llr,
+                    hipStream_t stream)
+{
+    const int64_t work = F * ((N + 3) / 4);
+    hipLaunchKernelGGL(k_awgn_llr, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, F, N, cw, sigma, scale,
+                       llr);
+    return check_launch(__func__);
+}
+
+int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream)
+{
+    int G = kMaxThreads / sc.Z;
+    if (G < 1)
+        G = 1;
+    const int threads = ((G * sc.Z + 63) / 64) * 64;
+    const size_t lds = (size_t)G * sc.K + 2 * (size_t)G * sc.Z;
+    hipLaunchKernelGGL(k_encode, dim3((unsigned)((F + G - 1) / G)), dim3(threads), lds, stream, sc, G, info, cw, F);
+    return check_launch(__func__);
+}
+
+}  // namespace ldpc

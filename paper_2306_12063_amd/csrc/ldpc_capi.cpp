@@ -1,0 +1,316 @@
+// Host side of libldpc: the C ABI, argument validation, the QC base-matrix
+// compiler (base matrix -> per-layer gather schedule) and launch planning.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ldpc_internal.h"
+
+namespace ldpc {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(LDPC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return LDPC_OK;
+}
+
+// Row y of the direct encoder (Sec. 1, eqs. 3-7; Sec. 2 eq. 12): h_b (column
+// K_b) must hold equal non-negative values in rows 0 and Mb-1 and exactly one
+// more non-negative value in between (row y); H_b2' must be the staircase of
+// zero shifts at (c, c) and (c+1, c). Returns y or -1.
+static int encoder_row(const int16_t *hbm, int Mb, int Nb)
+{
+    const int Kb = Nb - Mb;
+    if (Mb < 3)
+        return -1;
+    const int top = hbm[Kb], bottom = hbm[(Mb - 1) * Nb + Kb];
+    if (top < 0 || top != bottom)
+        return -1;
+    int y = -1, count = 0;
+    for (int i = 1; i + 1 < Mb; ++i)
+        if (hbm[i * Nb + Kb] >= 0) {
+            y = i;
+            ++count;
+        }
+    if (count != 1)
+        return -1;
+    for (int c = 0; c + 1 < Mb; ++c)
+        for (int i = 0; i < Mb; ++i) {
+            const int v = hbm[i * Nb + Kb + 1 + c];
+            if (v != ((i == c || i == c + 1) ? 0 : -1))
+                return -1;
+        }
+    return y;
+}
+
+int compile_sched(const int16_t *hbm, int Mb, int Nb, int Z, bool need_deg2, Sched *out)
+{
+    if (!hbm)
+        return fail(LDPC_EINVAL, "base matrix pointer is null");
+    if (Mb < 1 || Nb <= Mb || Z < 1)
+        return fail(LDPC_EINVAL, "bad code dimensions Mb=%d Nb=%d Z=%d (need Mb >= 1, Nb > Mb, Z >= 1)", Mb, Nb, Z);
+    if (Mb > kMaxMb || Nb > kMaxNb || Z > kMaxZ)
+        return fail(LDPC_ERANGE, "code Mb=%d Nb=%d Z=%d exceeds kernel limits (%d, %d, %d)", Mb, Nb, Z, kMaxMb, kMaxNb,
+                    kMaxZ);
+    Sched s;
+    memset(&s, 0, sizeof(s));
+    s.Z = Z;
+    s.Mb = Mb;
+    s.Nb = Nb;
+    s.N = Nb * Z;
+    s.K = (Nb - Mb) * Z;
+    s.M = Mb * Z;
+    for (int i = 0; i < Mb; ++i) {
+        int d = 0;
+        for (int j = 0; j < Nb; ++j) {
+            const int v = hbm[i * Nb + j];
+            if (v < -1 || v >= Z)
+                return fail(LDPC_EINVAL, "H_bm(%d,%d) = %d outside [-1, Z-1] for Z=%d", i, j, v, Z);
+            if (v < 0)
+                continue;
+            if (d >= kMaxDeg)
+                return fail(LDPC_ERANGE, "block row %d has more than %d non-zero blocks", i, kMaxDeg);
+            s.edge[i][d++] = ((uint32_t)j << 16) | (uint32_t)v;
+        }
+        if (need_deg2 && d < 2)
+            return fail(LDPC_EINVAL, "block row %d has check degree %d (< 2)", i, d);
+        s.deg[i] = d;
+        s.dmax = std::max(s.dmax, d);
+        s.E += d * Z;
+        s.hb[i] = hbm[i * Nb + (Nb - Mb)];
+    }
+    s.enc_y = encoder_row(hbm, Mb, Nb);
+    *out = s;
+    return LDPC_OK;
+}
+
+DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint)
+{
+    DecodeLaunch best{};
+    double best_util = -1.0;
+    const int kf = kf_hint > 0 ? kf_hint : 2;
+    for (int KF = kf; KF >= 1; --KF) {
+        for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
+            const int FW = G * KF;
+            if (FW > 64)
+                break;
+            int FWp = FW;
+            if (elem_bytes == 4)
+                FWp = FW | 1;                       // odd dword stride: consecutive rows hit distinct banks
+            else
+                while (FWp % 4 != 2)
+                    ++FWp;                          // odd dword stride for 2-byte elements
+            const size_t lds = (size_t)sc.N * FWp * elem_bytes;
+            if (lds > (size_t)kLdsBudget)
+                break;
+            const int threads = ((G * sc.Z + 63) / 64) * 64;
+            const double util = (double)(G * sc.Z) / threads;
+            if (util > best_util + 1e-9 || (util > best_util - 1e-9 && FW > best.FW)) {
+                best_util = util;
+                best = DecodeLaunch{G, KF, FW, FWp, threads, lds};
+            }
+        }
+        if (best_util > 0)
+            break;
+    }
+    return best;
+}
+
+}  // namespace ldpc
+
+using namespace ldpc;
+
+namespace {
+
+bool bad_ptrs(std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps)
+        if (!p)
+            return true;
+    return false;
+}
+
+int device_status(int rc, const char *what)
+{
+    // launchers already recorded the HIP error text; keep the entry point's name
+    if (rc != LDPC_OK && ldpc_last_error()[0] == '\0')
+        return fail(rc, "%s failed", what);
+    return rc;
+}
+
+int decode_common_checks(const Sched &sc, int64_t F, int max_iter)
+{
+    (void)sc;
+    if (F < 0)
+        return fail(LDPC_EINVAL, "negative frame count %lld", (long long)F);
+    if (max_iter < 1)
+        return fail(LDPC_EINVAL, "max_iter must be >= 1 (got %d)", max_iter);
+    return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ldpc_last_error(void) { return g_err; }
+
+void ldpc_cache_clear(void) {}
+
+int ldpc_code_info(const int16_t *hbm, int Mb, int Nb, int Z, int64_t out[8])
+{
+    clear_error();
+    if (!out || !hbm)
+        return fail(LDPC_EINVAL, "null pointer");
+    if (Mb < 1 || Nb <= Mb || Z < 1)
+        return fail(LDPC_EINVAL, "bad code dimensions Mb=%d Nb=%d Z=%d", Mb, Nb, Z);
+    int64_t E = 0, dmax = 0;
+    for (int i = 0; i < Mb; ++i) {
+        int64_t d = 0;
+        for (int j = 0; j < Nb; ++j) {
+            const int v = hbm[i * Nb + j];
+            if (v < -1 || v >= Z)
+                return fail(LDPC_EINVAL, "H_bm(%d,%d) = %d outside [-1, Z-1]", i, j, v);
+            d += v >= 0;
+        }
+        E += d * Z;
+        dmax = std::max(dmax, d);
+    }
+    out[0] = (int64_t)Nb * Z;
+    out[1] = (int64_t)(Nb - Mb) * Z;
+    out[2] = (int64_t)Mb * Z;
+    out[3] = E;
+    out[4] = dmax;
+    out[5] = encoder_row(hbm, Mb, Nb);
+    out[6] = Mb;
+    out[7] = Nb;
+    return LDPC_OK;
+}
+
+int ldpc_encode(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, uint8_t *cw, int64_t F,
+                void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, false, &sc);
+    if (rc)
+        return rc;
+    if (sc.enc_y < 0)
+        return fail(LDPC_ESTRUCT, "base matrix lacks the dual-diagonal parity structure of the direct encoder");
+    if (F < 0)
+        return fail(LDPC_EINVAL, "negative frame count");
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({info, cw}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    if (sc.Mb > 31)
+        return fail(LDPC_ERANGE, "encoder supports at most 31 block rows");
+    return device_status(launch_encode(sc, info, cw, F, (hipStream_t)stream), "ldpc_encode");
+}
+
+int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                    float alpha, int early_term, const float *w, uint8_t *bits, float *post, int32_t *iters,
+                    uint8_t *ok, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    const DecodeLaunch lc = plan_decode(sc, 4, 2);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    return device_status(launch_decode_f32(sc, lc, llr, nullptr, F, max_iter, alpha, early_term, w, bits, post,
+                                           iters, ok, (hipStream_t)stream),
+                         "ldpc_decode_f32");
+}
+
+int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                   int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits, int16_t *post,
+                   int32_t *iters, uint8_t *ok, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (offset < 0 || offset > 127)
+        return fail(LDPC_EINVAL, "offset must be in [0, 127] (got %d)", offset);
+    if (wq < 0 || wq > 31)
+        return fail(LDPC_EINVAL, "wq must be in [0, 31] (got %d)", wq);
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    const DecodeLaunch lc = plan_decode(sc, 2, 2);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    return device_status(launch_decode_i8(sc, lc, llr, nullptr, F, max_iter, offset, wq, wq_table, early_term, bits,
+                                          post, iters, ok, (hipStream_t)stream),
+                         "ldpc_decode_i8");
+}
+
+int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream)
+{
+    clear_error();
+    if (F < 0 || K < 0)
+        return fail(LDPC_EINVAL, "negative size");
+    if (F == 0 || K == 0)
+        return LDPC_OK;
+    if (!info)
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_random_bits(seed, F, K, info, (hipStream_t)stream), "ldpc_random_bits");
+}
+
+int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale, float *llr,
+                  void *stream)
+{
+    clear_error();
+    if (F < 0 || N < 0)
+        return fail(LDPC_EINVAL, "negative size");
+    if (F == 0 || N == 0)
+        return LDPC_OK;
+    if (bad_ptrs({cw, llr}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    if (N >= (int64_t(1) << 34))
+        return fail(LDPC_ERANGE, "frame length too large for the noise counter");
+    return device_status(launch_awgn_llr(seed, F, N, cw, sigma, scale, llr, (hipStream_t)stream), "ldpc_awgn_llr");
+}
+
+int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return fail(LDPC_EINVAL, "negative size");
+    if (n == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, q}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_quantize_i8(llr, q, n, scale, (hipStream_t)stream), "ldpc_quantize_i8");
+}
+
+}  // extern "C"

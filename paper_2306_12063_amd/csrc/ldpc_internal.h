@@ -1,0 +1,72 @@
+// Internal declarations of libldpc (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ldpc.h"
+
+namespace ldpc {
+
+constexpr int kMaxMb = LDPC_MAX_MB;
+constexpr int kMaxNb = LDPC_MAX_NB;
+constexpr int kMaxDeg = LDPC_MAX_DEG;
+constexpr int kMaxZ = LDPC_MAX_Z;
+// Largest workgroup the decode kernels are compiled for.
+constexpr int kMaxThreads = 256;
+// Dynamic LDS a decode workgroup may take (two workgroups fit one CU).
+constexpr int kLdsBudget = 64 * 1024;
+
+// Compiled form of a base matrix: the gather schedule of the layered decoder
+// and the encoder's parity-column data. It is small enough to travel as a
+// kernel argument, so single-code launches need no device-side tables.
+//
+// For block row i, edges e = 0 .. deg[i]-1 are the non-zero blocks in
+// ascending block column; edge[i][e] = (col << 16) | shift. Check row r of
+// block row i reaches variable col*Z + (r + shift) mod Z through edge e.
+struct Sched {
+    int32_t Z, Mb, Nb, N, K, M, E, dmax;
+    int32_t enc_y;             // row y of h_b for the direct encoder, or -1
+    int32_t hb[kMaxMb];        // h_b = column K_b of H_bm (-1 = zero block)
+    int32_t deg[kMaxMb];
+    uint32_t edge[kMaxMb][kMaxDeg];
+};
+
+// Builds the schedule; returns LDPC_OK, LDPC_EINVAL or LDPC_ERANGE and sets
+// the thread's error string on failure. need_deg2: every check row must have
+// at least two edges (decoders); need_enc: the encoder structure must hold.
+int compile_sched(const int16_t *hbm, int Mb, int Nb, int Z, bool need_deg2, Sched *out);
+
+// Thread-local error string helpers. check_launch() turns a pending HIP
+// launch error into LDPC_EDEVICE with the runtime's message.
+int fail(int code, const char *fmt, ...);
+void clear_error();
+int check_launch(const char *what);
+
+// Launch configuration of a decode kernel.
+struct DecodeLaunch {
+    int G;       // frame groups per workgroup (each group has Z threads)
+    int KF;      // frames per thread
+    int FW;      // frames per workgroup = G*KF
+    int FWp;     // LDS row stride in elements (FW, padded against bank conflicts)
+    int threads; // workgroup size
+    size_t lds;  // dynamic LDS bytes
+};
+
+// Kernel launchers (decode_kernels.hip). Return LDPC_OK or LDPC_EDEVICE.
+int launch_decode_f32(const Sched &sc, const DecodeLaunch &lc, const float *llr, const int64_t *fidx, int64_t F,
+                      int max_iter, float alpha, int early_term, const float *w, uint8_t *bits, float *post,
+                      int32_t *iters, uint8_t *ok, hipStream_t stream);
+int launch_decode_i8(const Sched &sc, const DecodeLaunch &lc, const int8_t *llr, const int64_t *fidx, int64_t F,
+                     int max_iter, int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits,
+                     int16_t *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
+int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream);
+int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
+int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream);
+int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale, float *llr,
+                    hipStream_t stream);
+
+// Picks G/KF for a code and element size (4 for FP32, 2 for int16 posteriors).
+DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint);
+
+}  // namespace ldpc

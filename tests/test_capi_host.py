@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every entry point include/ldpc.h declares, code descriptions are
+right, and invalid arguments are rejected before anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+import paper_2306_12063_amd as P
+from helpers import dense_h
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ldpc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(ldpc_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_entry_point():
+    names = _declared()
+    assert "ldpc_decode_f32" in names and "ldpc_encode" in names
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(P.EXPORTS) == names
+
+
+def test_code_info_matches_definition():
+    for rate in synth.WIFI_RATES:
+        h = synth.wifi_code(rate, 81)
+        info = P.ldpc_code_info(h, 81)
+        H = dense_h(h, 81)
+        assert info["N"] == H.shape[1] and info["M"] == H.shape[0]
+        assert info["K"] == H.shape[1] - H.shape[0]
+        assert info["E"] == int(H.sum())
+        assert info["dmax"] == int(H.sum(axis=1).max())
+        assert info["enc_y"] == (h.shape[0] - 1) // 2
+    g = synth.wifi_code("1/2", 27)
+    g[0, 12] = 3
+    assert P.ldpc_code_info(g, 27)["enc_y"] == -1
+
+
+def _call_decode(h, Z, F=0, max_iter=10):
+    h = np.ascontiguousarray(h, np.int16)
+    Mb, Nb = h.shape
+    rc = P.lib().ldpc_decode_f32(h.ctypes.data_as(C.c_void_p), Mb, Nb, Z, None, F, max_iter, 0.75, 1, None,
+                                 None, None, None, None, None)
+    return rc, P.ldpc_last_error()
+
+
+def test_validation_errors_without_gpu():
+    h = synth.wifi_code("1/2", 27)
+    assert _call_decode(h, 27, F=0)[0] == P.LDPC_OK          # empty batch is a no-op
+    bad = h.copy()
+    bad[2, 3] = 27
+    rc, msg = _call_decode(bad, 27)
+    assert rc == P.LDPC_EINVAL and "outside" in msg
+    rc, _ = _call_decode(h, 27, max_iter=0)
+    assert rc == P.LDPC_EINVAL
+    rc, _ = _call_decode(h, 27, F=-1)
+    assert rc == P.LDPC_EINVAL
+    deg1 = np.full((2, 4), -1, np.int16)
+    deg1[0, :2] = 0
+    deg1[1, 2] = 0
+    rc, msg = _call_decode(deg1, 3)
+    assert rc == P.LDPC_EINVAL and "degree" in msg
+    rc, _ = _call_decode(np.zeros((3, 3), np.int16), 5)      # Nb <= Mb
+    assert rc == P.LDPC_EINVAL
+    rc, _ = _call_decode(np.zeros((2, 40), np.int16), 5)     # too many block columns
+    assert rc == P.LDPC_ERANGE
+    rc, _ = _call_decode(np.zeros((2, 4), np.int16), 300)    # Z beyond the kernel limit
+    assert rc == P.LDPC_ERANGE
+
+
+def test_null_device_pointers_rejected():
+    h = np.ascontiguousarray(synth.wifi_code("1/2", 27), np.int16)
+    rc = P.lib().ldpc_decode_f32(h.ctypes.data_as(C.c_void_p), 12, 24, 27, None, 5, 10, 0.75, 1, None,
+                                 None, None, None, None, None)
+    assert rc == P.LDPC_EINVAL and "null" in P.ldpc_last_error()
+    rc = P.lib().ldpc_decode_i8(h.ctypes.data_as(C.c_void_p), 12, 24, 27, None, 5, 10, 200, 0, None, 1,
+                                None, None, None, None, None)
+    assert rc == P.LDPC_EINVAL and "offset" in P.ldpc_last_error()
+
+
+def test_encoder_structure_rejected_without_gpu():
+    h = synth.wifi_code("2/3", 27)
+    h[7, 16] = 2          # h_b: bottom entry differs from the top one
+    h = np.ascontiguousarray(h, np.int16)
+    rc = P.lib().ldpc_encode(h.ctypes.data_as(C.c_void_p), 8, 24, 27, None, None, 4, None)
+    assert rc == P.LDPC_ESTRUCT
