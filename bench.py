@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=1024,
                     help="frames per rate and path in the CPU-oracle baseline sample")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB (a reference kernel "
+                         "of known traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -193,6 +196,13 @@ def main():
         "per_kernel": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()
                         if k not in ("alg_ops", "hbm_bytes")} for p in per],
     }
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_reference"] = {"bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu_baseline:
         nf = min(args.cpu_frames, F)
         for c in cases:
