@@ -23,8 +23,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 GPU = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _embed_jit_source():
+    """Writes _build/jit_source.cpp: jit_decode.hip as a C++ string for hipRTC."""
+    with open(os.path.join(CSRC, "jit_decode.hip")) as fh:
+        text = fh.read()
+    delim = "LDPCJIT"
+    assert ")" + delim not in text
+    out = os.path.join(OBJ, "jit_source.cpp")
+    with open(out, "w") as fh:
+        fh.write("// generated from csrc/jit_decode.hip by build.py\n"
+                 "namespace ldpc {\nextern const char kJitDecodeSource[];\n"
+                 f"const char kJitDecodeSource[] = R\"{delim}(\n{text}){delim}\";\n}}\n")
+    return out
+
+
 def _units():
     units = [("ldpc_capi.cpp", [], "ldpc_capi.o"),
+             ("jit.cpp", [], "jit.o"),
+             (os.path.join(OBJ, "jit_source.cpp"), [], "jit_source.o"),
              ("decode_dispatch.cpp", [], "decode_dispatch.o"),
              ("frame_kernels.hip", [], "frame_kernels.o")]
     for kind in ("f32", "i8"):
@@ -47,6 +63,7 @@ def _compile(unit, verbose):
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    _embed_jit_source()
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(lambda u: _compile(u, verbose), _units()))
@@ -57,7 +74,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         if verbose and m.strip():
             print(m)
     tmp = LIB + ".tmp"
-    link = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [o for o, _, _ in results]
+    link = (["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [o for o, _, _ in results]
+            + ["-lhiprtc"])
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -24,30 +24,43 @@
 
 namespace ldpc {
 
-// Hides a value from loop-invariant code motion. The gather addresses and
-// schedule words of every layer are the same in every iteration; hoisting
-// them out of the iteration loop would pin hundreds of registers, so they
-// are recomputed per layer from an opaque copy of the row and layer index.
-__device__ __forceinline__ int opaque_v(int x)
+// One edge of a block row, prepared for a launch's LDS layout: check row r
+// reaches element base + r*FWp, minus Z*FWp once r >= thr (the cyclic wrap
+// of (r + shift) mod Z). Built in LDS at kernel start; reading it from LDS
+// each layer also keeps the compiler from hoisting every layer's addresses
+// out of the iteration loop into registers.
+struct GatherEdge {
+    int base;   // (col*Z + shift) * FWp
+    int thr;    // Z - shift
+    int col;    // block column (weight-table index)
+    int pad;
+};
+
+template <int MB, int MAXD>
+__device__ __forceinline__ void build_gather_table(const Sched &sc, int FWp, GatherEdge (&tbl)[MB][MAXD])
 {
-    asm volatile("" : "+v"(x));
-    return x;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int e = 0; e < MAXD; ++e)
+            if ((int)threadIdx.x == ((i * MAXD + e) & 255)) {
+                GatherEdge ge{0, 1 << 30, 0, 0};
+                if (i < sc.Mb && e < sc.deg[i]) {
+                    const uint32_t ew = sc.edge[i][e];
+                    const int col = (int)(ew >> 16), s = (int)(ew & 0xffffu);
+                    ge.base = (col * sc.Z + s) * FWp;
+                    ge.thr = sc.Z - s;
+                    ge.col = col;
+                }
+                tbl[i][e] = ge;
+            }
 }
 
-__device__ __forceinline__ int opaque_s(int x)
+// LDS element (frame slot of rbase) that check row r reaches through edge ge;
+// rbase = r*FWp + slot, zfw = Z*FWp.
+__device__ __forceinline__ int gather_addr(const GatherEdge &ge, int r, int rbase, int zfw)
 {
-    asm volatile("" : "+s"(x));
-    return x;
-}
-
-// Element index (frame slot 0) of the variable that check row r reaches
-// through edge word ew = (col << 16) | shift.
-__device__ __forceinline__ int var_index(uint32_t ew, int r, int Z)
-{
-    const int col = (int)(ew >> 16);
-    int x = r + (int)(ew & 0xffffu);
-    x = (x >= Z) ? x - Z : x;
-    return col * Z + x;
+    return rbase + ge.base + ((r >= ge.thr) ? -zfw : 0);
 }
 
 __device__ __forceinline__ int edge_col(uint32_t ew) { return (int)(ew >> 16); }
@@ -90,22 +103,21 @@ __device__ __forceinline__ void store_frames(const TL *Ls, const int64_t *__rest
 }
 
 // 1 if any check row owned by this thread is unsatisfied by the hard
-// decisions of one frame slot.
+// decisions of the frame slot addressed by rbase.
 template <int MB, int MAXD, typename TL>
-__device__ __forceinline__ int rows_unsatisfied(const Sched &sc, const TL *Ls, int r, int FWp, int slot)
+__device__ __forceinline__ int rows_unsatisfied(const Sched &sc, const GatherEdge (&tbl)[MB][MAXD], const TL *Ls,
+                                                int r, int rbase, int zfw)
 {
     int bad = 0;
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         if (i < sc.Mb) {
-            const int li = opaque_s(i);
-            const int rr = opaque_v(r);
-            const int d = sc.deg[li];
+            const int d = sc.deg[i];
             int p = 0;
 #pragma unroll
             for (int e = 0; e < MAXD; ++e)
                 if (e < d)
-                    p ^= (Ls[var_index(sc.edge[li][e], rr, sc.Z) * FWp + slot] > (TL)0) ? 0 : 1;
+                    p ^= (Ls[gather_addr(tbl[i][e], r, rbase, zfw)] > (TL)0) ? 0 : 1;
             bad |= p;
         }
     }

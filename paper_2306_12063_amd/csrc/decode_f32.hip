@@ -25,6 +25,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
 {
     extern __shared__ float Ls[];
     __shared__ int unsat[64];
+    __shared__ GatherEdge tbl[MB][MAXD];
     const int Z = sc.Z, Mb = sc.Mb, Nb = sc.Nb;
     const int FW = G * KF;
     const int tid = threadIdx.x;
@@ -34,15 +35,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
     const int slot0 = g * KF;
     const int64_t f0 = (int64_t)blockIdx.x * FW;
 
+    build_gather_table<MB, MAXD>(sc, FWp, tbl);
     // Adding +0.0f turns a -0.0 input into +0.0, so that from here on the
     // sign bit of every value equals (value < 0), the paper's sgn with
     // sgn(-0) = +1 (-0 cannot reappear: x - x and x + (-x) round to +0).
     load_frames(Ls, llr, fidx, f0, F, FW, FWp, sc.N, [](float v) { return v + 0.0f; });
     if (tid < 64)
         unsat[tid] = 0;
+    const int rbase = r * FWp + slot0;
+    const int zfw = Z * FWp;
 
     float sm1[KF][MB], sm2[KF][MB];
-    uint32_t ssg[KF][MB];   // sign bits (1 = message negative) | argmin << 27
+    uint32_t ssg[KF][MB];   // sign bits (edge e at bit d-1-e; 1 = message negative) | argmin << 27
     bool act[KF];
     int itk[KF], okk[KF];
 #pragma unroll
@@ -63,30 +67,30 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             if (i < Mb) {
-                const int li = opaque_s(i);
-                const int rr = opaque_v(r);
-                const int d = sc.deg[li];
+                const int d = sc.deg[i];
                 int ix[MAXD];
 #pragma unroll
                 for (int e = 0; e < MAXD; ++e)
                     if (e < d)
-                        ix[e] = var_index(sc.edge[li][e], rr, Z) * FWp + slot0;
+                        ix[e] = gather_addr(tbl[i][e], r, rbase, zfw);
                 float Q[KF][MAXD];
 #pragma unroll
                 for (int k = 0; k < KF; ++k) {
                     if (act[k]) {
-                        const float om1 = sm1[k][i], om2 = sm2[k][i];
+                        const uint32_t om1 = __float_as_uint(sm1[k][i]), om2 = __float_as_uint(sm2[k][i]);
                         const uint32_t osg = ssg[k][i];
-                        const int oidx = (int)(osg >> 27);
+                        const uint32_t oidx = osg >> 27;
 #pragma unroll
                         for (int e = 0; e < MAXD; ++e) {
                             if (e < d) {
-                                float mag = (e == oidx) ? om2 : om1;
+                                uint32_t mag = (oidx == (uint32_t)e) ? om2 : om1;
                                 if (LEARNED)
-                                    mag = (t > 0 ? wt[((t - 1) * Mb + li) * Nb + edge_col(sc.edge[li][e])] : 0.0f) *
-                                          mag;
-                                const float ro = ((osg >> e) & 1u) ? -mag : mag;
-                                Q[k][e] = Ls[ix[e] + k] - ro;
+                                    mag = __float_as_uint(
+                                        (t > 0 ? wt[((t - 1) * Mb + i) * Nb + tbl[i][e].col] : 0.0f) *
+                                        __uint_as_float(mag));
+                                // message sign: bit d-1-e of the state moved to bit 31
+                                const uint32_t ro = mag | ((osg << (32 - d + e)) & 0x80000000u);
+                                Q[k][e] = Ls[ix[e] + k] - __uint_as_float(ro);
                             }
                         }
                     }
@@ -95,23 +99,21 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
                 for (int k = 0; k < KF; ++k) {
                     if (act[k]) {
                         float m1 = INFINITY, m2 = INFINITY;
-                        int idx = 0;
-                        uint32_t neg = 0;
+                        uint32_t idx = 0, neg = 0;
 #pragma unroll
                         for (int e = 0; e < MAXD; ++e) {
                             if (e < d) {
                                 const float a = fabsf(Q[k][e]);
-                                if (a < m1) {
-                                    m2 = m1;
-                                    m1 = a;
-                                    idx = e;
-                                } else if (a < m2) {
-                                    m2 = a;
-                                }
-                                neg |= (__float_as_uint(Q[k][e]) >> 31) << e;
+                                idx = (a < m1) ? (uint32_t)e : idx;
+                                m2 = __builtin_amdgcn_fmed3f(a, m1, m2);
+                                m1 = fminf(m1, a);
+                                // shift the sign bit of Q in from the right
+                                neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(Q[k][e]), 31);
                             }
                         }
+                        // sign of the message to edge e: parity of all sign bits but e's own
                         const uint32_t par = (uint32_t)__popc(neg) & 1u;
+                        const uint32_t parbit = par << 31;
                         const uint32_t sgm = neg ^ ((0u - par) & ((1u << d) - 1u));
                         float n1 = 0.0f, n2 = 0.0f;
                         if (!LEARNED) {
@@ -121,18 +123,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
 #pragma unroll
                         for (int e = 0; e < MAXD; ++e) {
                             if (e < d) {
-                                float mag;
+                                uint32_t mag;
                                 if (LEARNED)
-                                    mag = wt[(t * Mb + li) * Nb + edge_col(sc.edge[li][e])] * ((e == idx) ? m2 : m1);
+                                    mag = __float_as_uint(wt[(t * Mb + i) * Nb + tbl[i][e].col] *
+                                                          ((idx == (uint32_t)e) ? m2 : m1));
                                 else
-                                    mag = (e == idx) ? n2 : n1;
-                                const float rn = ((sgm >> e) & 1u) ? -mag : mag;
-                                Ls[ix[e] + k] = Q[k][e] + rn;
+                                    mag = __float_as_uint((idx == (uint32_t)e) ? n2 : n1);
+                                const uint32_t rn = mag | ((__float_as_uint(Q[k][e]) ^ parbit) & 0x80000000u);
+                                Ls[ix[e] + k] = Q[k][e] + __uint_as_float(rn);
                             }
                         }
                         sm1[k][i] = LEARNED ? m1 : n1;
                         sm2[k][i] = LEARNED ? m2 : n2;
-                        ssg[k][i] = sgm | ((uint32_t)idx << 27);
+                        ssg[k][i] = sgm | (idx << 27);
                     }
                 }
             }
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_f32(
         if (et || t == max_iter - 1) {
 #pragma unroll
             for (int k = 0; k < KF; ++k)
-                if (act[k] && rows_unsatisfied<MB, MAXD>(sc, Ls, r, FWp, slot0 + k))
+                if (act[k] && rows_unsatisfied<MB, MAXD>(sc, tbl, Ls, r, rbase + k, zfw))
                     unsat[slot0 + k] = 1;
             __syncthreads();
             const int any = settle_frames<KF>(unsat, slot0, t, max_iter, et, act, itk, okk);

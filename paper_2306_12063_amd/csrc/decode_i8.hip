@@ -29,6 +29,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
 {
     extern __shared__ int16_t L16[];
     __shared__ int unsat[64];
+    __shared__ GatherEdge tbl[MB][MAXD];
     const int Z = sc.Z, Mb = sc.Mb, Nb = sc.Nb;
     const int FW = G * KF;
     const int tid = threadIdx.x;
@@ -38,9 +39,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
     const int slot0 = g * KF;
     const int64_t f0 = (int64_t)blockIdx.x * FW;
 
+    build_gather_table<MB, MAXD>(sc, FWp, tbl);
     load_frames(L16, llr, fidx, f0, F, FW, FWp, sc.N, [](int8_t v) { return (int16_t)v; });
     if (tid < 64)
         unsat[tid] = 0;
+    const int rbase = r * FWp + slot0;
+    const int zfw = Z * FWp;
 
     // Compressed row state: smg = m1 | m2 << 8 (output magnitudes in modes
     // 0/1, raw minima in mode 2); ssg = sign bits (1 = negative) | argmin << 27.
@@ -64,14 +68,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             if (i < Mb) {
-                const int li = opaque_s(i);
-                const int rr = opaque_v(r);
-                const int d = sc.deg[li];
+                const int li = i;
+                const int d = sc.deg[i];
                 int ix[MAXD];
 #pragma unroll
                 for (int e = 0; e < MAXD; ++e)
                     if (e < d)
-                        ix[e] = var_index(sc.edge[li][e], rr, Z) * FWp + slot0;
+                        ix[e] = gather_addr(tbl[i][e], r, rbase, zfw);
                 int Q[KF][MAXD];
 #pragma unroll
                 for (int k = 0; k < KF; ++k) {
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
                             if (e < d) {
                                 int mag = (e == oidx) ? om2 : om1;
                                 if (MODE == 2)
-                                    mag = t > 0 ? norm_mag(wtab[((t - 1) * Mb + li) * Nb + edge_col(sc.edge[li][e])], mag)
+                                    mag = t > 0 ? norm_mag(wtab[((t - 1) * Mb + li) * Nb + tbl[i][e].col], mag)
                                                 : 0;
                                 const int ro = ((osg >> e) & 1u) ? -mag : mag;
                                 Q[k][e] = sat16((int)L16[ix[e] + k] - ro);
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
                             if (e < d) {
                                 int mag;
                                 if (MODE == 2)
-                                    mag = norm_mag(wtab[(t * Mb + li) * Nb + edge_col(sc.edge[li][e])],
+                                    mag = norm_mag(wtab[(t * Mb + li) * Nb + tbl[i][e].col],
                                                    (e == idx) ? m2 : m1);
                                 else
                                     mag = (e == idx) ? n2 : n1;
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_decode_i8(
         if (et || t == max_iter - 1) {
 #pragma unroll
             for (int k = 0; k < KF; ++k)
-                if (act[k] && rows_unsatisfied<MB, MAXD>(sc, L16, r, FWp, slot0 + k))
+                if (act[k] && rows_unsatisfied<MB, MAXD>(sc, tbl, L16, r, rbase + k, zfw))
                     unsat[slot0 + k] = 1;
             __syncthreads();
             const int any = settle_frames<KF>(unsat, slot0, t, max_iter, et, act, itk, okk);

@@ -1,0 +1,166 @@
+// Run-time specialisation of the decode kernel (hipRTC).
+//
+// The base matrix is turned into a prelude of compile-time constants
+// (degrees, block columns, shifts, launch layout) that is prepended to the
+// kernel source in jit_decode.hip, compiled for the current device's
+// architecture and cached per (device, code, layout, arithmetic path). Each
+// layer of the specialised kernel is straight-line code.
+#include <hip/hiprtc.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+
+#include "ldpc_internal.h"
+
+namespace ldpc {
+
+// Kernel source, embedded at build time from jit_decode.hip.
+extern const char kJitDecodeSource[];
+
+namespace {
+
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+
+std::mutex g_mu;
+std::unordered_map<std::string, JitKernel> g_cache;
+
+std::string prelude(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
+{
+    std::ostringstream o;
+    o << "#define LDPC_Z " << sc.Z << "\n#define LDPC_MB " << sc.Mb << "\n#define LDPC_NB " << sc.Nb
+      << "\n#define LDPC_N " << sc.N << "\n#define LDPC_MAXD " << sc.dmax << "\n#define LDPC_G " << lc.G
+      << "\n#define LDPC_KF " << lc.KF << "\n#define LDPC_FWP " << lc.FWp << "\n#define LDPC_THREADS " << lc.threads
+      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n";
+    o << "__device__ constexpr int kDeg[" << sc.Mb << "] = {";
+    for (int i = 0; i < sc.Mb; ++i)
+        o << sc.deg[i] << (i + 1 < sc.Mb ? "," : "};\n");
+    for (int pass = 0; pass < 2; ++pass) {
+        o << "__device__ constexpr int " << (pass ? "kShift" : "kCol") << "[" << sc.Mb << "][" << sc.dmax << "] = {";
+        for (int i = 0; i < sc.Mb; ++i) {
+            o << "{";
+            for (int e = 0; e < sc.dmax; ++e) {
+                const int v = e < sc.deg[i] ? (pass ? (int)(sc.edge[i][e] & 0xffffu) : (int)(sc.edge[i][e] >> 16)) : 0;
+                o << v << (e + 1 < sc.dmax ? "," : "");
+            }
+            o << "}" << (i + 1 < sc.Mb ? "," : "};\n");
+        }
+    }
+    return o.str();
+}
+
+// Compiles specialised source for an architecture; needs no device.
+int rtc_compile(const std::string &src, const std::string &arch, std::string *code)
+{
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "ldpc_jit_decode.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(LDPC_EDEVICE, "hiprtcCreateProgram failed");
+    const std::string archopt = "--offload-arch=" + arch;
+    const char *opts[] = {archopt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n, '\0');
+        if (n)
+            hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(LDPC_EDEVICE, "hipRTC compile failed: %.400s", log.c_str());
+    }
+    size_t size = 0;
+    hiprtcGetCodeSize(prog, &size);
+    code->assign(size, '\0');
+    hiprtcGetCode(prog, &(*code)[0]);
+    hiprtcDestroyProgram(&prog);
+    return LDPC_OK;
+}
+
+int load(const std::string &code, JitKernel *out)
+{
+    hipModule_t mod;
+    if (hipModuleLoadData(&mod, code.data()) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipModuleLoadData failed: %s", hipGetErrorString(hipGetLastError()));
+    hipFunction_t fn;
+    if (hipModuleGetFunction(&fn, mod, "ldpc_jit_decode") != hipSuccess) {
+        hipModuleUnload(mod);
+        return fail(LDPC_EDEVICE, "hipModuleGetFunction failed");
+    }
+    out->mod = mod;
+    out->fn = fn;
+    return LDPC_OK;
+}
+
+int get_kernel(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipGetDevice failed");
+    const std::string pre = prelude(sc, lc, path, mode);
+    const std::string key = std::to_string(dev) + "\n" + pre;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        *fn = it->second.fn;
+        return LDPC_OK;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipGetDeviceProperties failed");
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos)
+        arch = arch.substr(0, colon);
+    std::string code;
+    int rc = rtc_compile(pre + kJitDecodeSource, arch, &code);
+    if (rc)
+        return rc;
+    JitKernel k;
+    if ((rc = load(code, &k)))
+        return rc;
+    g_cache.emplace(key, k);
+    *fn = k.fn;
+    return LDPC_OK;
+}
+
+}  // namespace
+
+bool jit_enabled()
+{
+    const char *v = getenv("LDPC_JIT");
+    return !(v && v[0] == '0');
+}
+
+void jit_cache_clear()
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &kv : g_cache)
+        hipModuleUnload(kv.second.mod);
+    g_cache.clear();
+}
+
+int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
+                      const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
+                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream)
+{
+    hipFunction_t fn;
+    int rc = get_kernel(sc, lc, path, mode, &fn);
+    if (rc)
+        return rc;
+    long long Fll = (long long)F;
+    void *args[] = {(void *)&llr, (void *)&fidx, (void *)&Fll, (void *)&max_iter, (void *)&alpha, (void *)&offset,
+                    (void *)&wq, (void *)&et, (void *)&wt, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
+    const unsigned blocks = (unsigned)((F + lc.FW - 1) / lc.FW);
+    if (hipModuleLaunchKernel(fn, blocks, 1, 1, lc.threads, 1, 1, 0, stream, args, nullptr) != hipSuccess)
+        return fail(LDPC_EDEVICE, "decode launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return LDPC_OK;
+}
+
+}  // namespace ldpc

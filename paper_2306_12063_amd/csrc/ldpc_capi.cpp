@@ -171,7 +171,7 @@ extern "C" {
 
 const char *ldpc_last_error(void) { return g_err; }
 
-void ldpc_cache_clear(void) {}
+void ldpc_cache_clear(void) { jit_cache_clear(); }
 
 int ldpc_code_info(const int16_t *hbm, int Mb, int Nb, int Z, int64_t out[8])
 {
@@ -242,6 +242,9 @@ int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr,
     const DecodeLaunch lc = plan_decode(sc, 4, 2);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    if (jit_enabled())
+        return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits,
+                                 post, iters, ok, (hipStream_t)stream);
     return device_status(launch_decode_f32(sc, lc, llr, nullptr, F, max_iter, alpha, early_term, w, bits, post,
                                            iters, ok, (hipStream_t)stream),
                          "ldpc_decode_f32");
@@ -269,6 +272,9 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
     const DecodeLaunch lc = plan_decode(sc, 2, 2);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    if (jit_enabled())
+        return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset,
+                                 wq, early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream);
     return device_status(launch_decode_i8(sc, lc, llr, nullptr, F, max_iter, offset, wq, wq_table, early_term, bits,
                                           post, iters, ok, (hipStream_t)stream),
                          "ldpc_decode_i8");

@@ -66,6 +66,14 @@ int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipSt
 int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale, float *llr,
                     hipStream_t stream);
 
+// Run-time specialised decode kernels (jit.cpp). path: 0 FP32, 1 int8;
+// mode as in jit_decode.hip. LDPC_JIT=0 in the environment disables them.
+bool jit_enabled();
+void jit_cache_clear();
+int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
+                      const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
+                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
+
 // Picks G/KF for a code and element size (4 for FP32, 2 for int16 posteriors).
 DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint);
 
