@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=1 << 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default decode layout")
     ap.add_argument("--cpu-frames", type=int, default=1024,
                     help="frames per rate and path in the CPU-oracle baseline sample")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -137,6 +138,14 @@ def main():
                               iters=torch.empty(F, dtype=torch.int32, device=dev),
                               ok=torch.empty(F, dtype=torch.uint8, device=dev)))
     torch.cuda.synchronize()
+    # Untimed: pick each code's fastest decode layout (frames per workgroup and
+    # per thread, register variant) with the library's autotuner.
+    layouts = {}
+    if not args.no_autotune:
+        for c in cases:
+            cfg = P.ldpc_autotune_decode(c["hbm"], Z, path=c["path"], max_iter=ITERS, F=min(F, 16384))
+            layouts[f"{c['path']} {c['rate']}"] = {k: cfg[k] for k in ("G", "KF", "threads", "hoist")}
+    torch.cuda.synchronize()
 
     def launch(c):
         if c["path"] == "f32":
@@ -191,7 +200,8 @@ def main():
         "config": {"workload": f"Wi-Fi-shaped synthetic QC-LDPC codes, Z=81 (N=1944), rates 1/2 2/3 3/4 5/6; "
                                f"{F} frames per rate at Eb/N0={EBN0_DB} dB; FP32 NMS alpha={ALPHA} and "
                                f"int8 OMS offset={OFFSET}; {ITERS} fixed iterations, early termination off",
-                   "frames_per_launch": F, "iterations": ITERS, "parallelism": "single GPU"},
+                   "frames_per_launch": F, "iterations": ITERS, "parallelism": "single GPU",
+                   "layouts": layouts},
         "roofline": roofline,
         "per_kernel": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()
                         if k not in ("alg_ops", "hbm_bytes")} for p in per],

@@ -117,6 +117,20 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
                    int32_t *iters, uint8_t *ok, void *stream);
 
 /*
+ * Decode-layout autotuner. Times the code-specialised decode kernel of
+ * `path` (0 FP32, 1 int8) over candidate layouts -- frame groups per
+ * workgroup, frames per thread, and whether gather addresses stay in
+ * registers across iterations -- on F zero-valued frames at max_iter fixed
+ * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
+ * this code in this process (until ldpc_cache_clear). out[5] receives
+ * {G, KF, FWp, threads, hoist} of the winner and *ms its time per launch.
+ * Synchronises `stream`; allocates and frees temporary device buffers.
+ * LDPC_ERANGE if run-time specialisation is disabled (LDPC_JIT=0).
+ */
+int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
+                         int32_t out[5], float *ms, void *stream);
+
+/*
  * Seeded information bits from Philox4x32-10 (Salmon et al., SC'11):
  * bit k of frame f is bit (k mod 32) of word (k/32 mod 4) of
  * Philox(counter = {k/128, f, 0, 0}, key = {seed low, seed high}).

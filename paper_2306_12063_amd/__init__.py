@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
-    "ldpc_quantize_i8", "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -36,6 +36,7 @@ EXPORTS = {
     "ldpc_random_bits": ([_u64, _i64, _i64, _p, _p], _i32),
     "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p], _i32),
     "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
+    "ldpc_autotune_decode": ([_p, _i32, _i32, _i32, _i32, _i32, _i64, _p, _p, _p], _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -186,6 +187,20 @@ def ldpc_decode_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, wq_table=None, earl
                                 _opt(post, torch.int16, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
                                 _opt(ok, torch.uint8, "ok", (F,)), _stream(stream)), "ldpc_decode_i8")
     return bits, post, iters, ok
+
+
+def ldpc_autotune_decode(hbm, Z, path="f32", max_iter=10, F=16384, stream=None):
+    """Times candidate decode layouts for this code and keeps the fastest.
+    Returns dict(G, KF, FWp, threads, hoist, ms)."""
+    h = _hbm(hbm)
+    out = np.zeros(5, np.int32)
+    ms = np.zeros(1, np.float32)
+    p = {"f32": 0, "i8": 1}[path]
+    _check(lib().ldpc_autotune_decode(_hptr(h), h.shape[0], h.shape[1], Z, p, int(max_iter), int(F),
+                                      out.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p),
+                                      _stream(stream)), "ldpc_autotune_decode")
+    return dict(G=int(out[0]), KF=int(out[1]), FWp=int(out[2]), threads=int(out[3]), hoist=int(out[4]),
+                ms=float(ms[0]))
 
 
 def ldpc_quantize_i8(llr, scale=4.0, out=None, stream=None):

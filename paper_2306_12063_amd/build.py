@@ -40,6 +40,7 @@ def _embed_jit_source():
 def _units():
     units = [("ldpc_capi.cpp", [], "ldpc_capi.o"),
              ("jit.cpp", [], "jit.o"),
+             ("tune.cpp", [], "tune.o"),
              (os.path.join(OBJ, "jit_source.cpp"), [], "jit_source.o"),
              ("decode_dispatch.cpp", [], "decode_dispatch.o"),
              ("frame_kernels.hip", [], "frame_kernels.o")]

@@ -38,7 +38,8 @@ std::string prelude(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
     o << "#define LDPC_Z " << sc.Z << "\n#define LDPC_MB " << sc.Mb << "\n#define LDPC_NB " << sc.Nb
       << "\n#define LDPC_N " << sc.N << "\n#define LDPC_MAXD " << sc.dmax << "\n#define LDPC_G " << lc.G
       << "\n#define LDPC_KF " << lc.KF << "\n#define LDPC_FWP " << lc.FWp << "\n#define LDPC_THREADS " << lc.threads
-      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n";
+      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n#define LDPC_HOIST " << lc.hoist
+      << "\n";
     o << "__device__ constexpr int kDeg[" << sc.Mb << "] = {";
     for (int i = 0; i < sc.Mb; ++i)
         o << sc.deg[i] << (i + 1 < sc.Mb ? "," : "};\n");

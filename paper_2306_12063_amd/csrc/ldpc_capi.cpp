@@ -101,6 +101,25 @@ int compile_sched(const int16_t *hbm, int Mb, int Nb, int Z, bool need_deg2, Sch
     return LDPC_OK;
 }
 
+DecodeLaunch make_launch(const Sched &sc, int elem_bytes, int G, int KF, int max_threads)
+{
+    DecodeLaunch lc{};
+    const int FW = G * KF;
+    if (G < 1 || KF < 1 || FW > 64 || G * sc.Z > max_threads)
+        return lc;
+    int FWp = FW;
+    if (elem_bytes == 4)
+        FWp = FW | 1;                       // odd dword stride: consecutive rows hit distinct banks
+    else
+        while (FWp % 4 != 2)
+            ++FWp;                          // odd dword stride for 2-byte elements
+    const size_t lds = (size_t)sc.N * FWp * elem_bytes;
+    if (lds > (size_t)kLdsBudget)
+        return lc;
+    lc = DecodeLaunch{G, KF, FW, FWp, ((G * sc.Z + 63) / 64) * 64, lds, 1};
+    return lc;
+}
+
 DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint)
 {
     DecodeLaunch best{};
@@ -108,23 +127,13 @@ DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint)
     const int kf = kf_hint > 0 ? kf_hint : 2;
     for (int KF = kf; KF >= 1; --KF) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
-            const int FW = G * KF;
-            if (FW > 64)
+            const DecodeLaunch lc = make_launch(sc, elem_bytes, G, KF, kMaxThreads);
+            if (lc.G < 1)
                 break;
-            int FWp = FW;
-            if (elem_bytes == 4)
-                FWp = FW | 1;                       // odd dword stride: consecutive rows hit distinct banks
-            else
-                while (FWp % 4 != 2)
-                    ++FWp;                          // odd dword stride for 2-byte elements
-            const size_t lds = (size_t)sc.N * FWp * elem_bytes;
-            if (lds > (size_t)kLdsBudget)
-                break;
-            const int threads = ((G * sc.Z + 63) / 64) * 64;
-            const double util = (double)(G * sc.Z) / threads;
-            if (util > best_util + 1e-9 || (util > best_util - 1e-9 && FW > best.FW)) {
+            const double util = (double)(G * sc.Z) / lc.threads;
+            if (util > best_util + 1e-9 || (util > best_util - 1e-9 && lc.FW > best.FW)) {
                 best_util = util;
-                best = DecodeLaunch{G, KF, FW, FWp, threads, lds};
+                best = lc;
             }
         }
         if (best_util > 0)
@@ -171,7 +180,11 @@ extern "C" {
 
 const char *ldpc_last_error(void) { return g_err; }
 
-void ldpc_cache_clear(void) { jit_cache_clear(); }
+void ldpc_cache_clear(void)
+{
+    jit_cache_clear();
+    tune_cache_clear();
+}
 
 int ldpc_code_info(const int16_t *hbm, int Mb, int Nb, int Z, int64_t out[8])
 {
@@ -239,12 +252,14 @@ int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr,
         return LDPC_OK;
     if (bad_ptrs({llr, bits, iters}))
         return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
-    const DecodeLaunch lc = plan_decode(sc, 4, 2);
+    DecodeLaunch lc = plan_decode(sc, 4, 2);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
-    if (jit_enabled())
+    if (jit_enabled()) {
+        tuned_launch(sc, 0, &lc);
         return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits,
                                  post, iters, ok, (hipStream_t)stream);
+    }
     return device_status(launch_decode_f32(sc, lc, llr, nullptr, F, max_iter, alpha, early_term, w, bits, post,
                                            iters, ok, (hipStream_t)stream),
                          "ldpc_decode_f32");
@@ -269,15 +284,44 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
         return LDPC_OK;
     if (bad_ptrs({llr, bits, iters}))
         return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
-    const DecodeLaunch lc = plan_decode(sc, 2, 2);
+    DecodeLaunch lc = plan_decode(sc, 2, 2);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
-    if (jit_enabled())
+    if (jit_enabled()) {
+        tuned_launch(sc, 1, &lc);
         return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset,
                                  wq, early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream);
+    }
     return device_status(launch_decode_i8(sc, lc, llr, nullptr, F, max_iter, offset, wq, wq_table, early_term, bits,
                                           post, iters, ok, (hipStream_t)stream),
                          "ldpc_decode_i8");
+}
+
+int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
+                         int32_t out[5], float *ms, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if (path != 0 && path != 1)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (max_iter < 1 || F < 1)
+        return fail(LDPC_EINVAL, "max_iter and F must be >= 1");
+    if (!out || !ms)
+        return fail(LDPC_EINVAL, "null output pointer");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the autotuner needs run-time specialised kernels (LDPC_JIT=0 is set)");
+    DecodeLaunch best{};
+    if ((rc = autotune_decode(sc, path, max_iter, F, (hipStream_t)stream, &best, ms)))
+        return rc;
+    out[0] = best.G;
+    out[1] = best.KF;
+    out[2] = best.FWp;
+    out[3] = best.threads;
+    out[4] = best.hoist;
+    return LDPC_OK;
 }
 
 int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream)

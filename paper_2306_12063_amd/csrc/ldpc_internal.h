@@ -14,8 +14,10 @@ constexpr int kMaxDeg = LDPC_MAX_DEG;
 constexpr int kMaxZ = LDPC_MAX_Z;
 // Largest workgroup the decode kernels are compiled for.
 constexpr int kMaxThreads = 256;
+// Largest workgroup of a run-time specialised decode kernel.
+constexpr int kMaxJitThreads = 512;
 // Dynamic LDS a decode workgroup may take (two workgroups fit one CU).
-constexpr int kLdsBudget = 64 * 1024;
+constexpr int kLdsBudget = 56 * 1024;
 
 // Compiled form of a base matrix: the gather schedule of the layered decoder
 // and the encoder's parity-column data. It is small enough to travel as a
@@ -50,7 +52,8 @@ struct DecodeLaunch {
     int FW;      // frames per workgroup = G*KF
     int FWp;     // LDS row stride in elements (FW, padded against bank conflicts)
     int threads; // workgroup size
-    size_t lds;  // dynamic LDS bytes
+    size_t lds;  // LDS bytes of the posteriors
+    int hoist = 1;  // specialised kernels: keep gather addresses in registers
 };
 
 // Kernel launchers (decode_kernels.hip). Return LDPC_OK or LDPC_EDEVICE.
@@ -76,5 +79,15 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
 
 // Picks G/KF for a code and element size (4 for FP32, 2 for int16 posteriors).
 DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint);
+// Layout for a given G and KF (G < 1 in the result if it does not fit).
+DecodeLaunch make_launch(const Sched &sc, int elem_bytes, int G, int KF, int max_threads);
+
+// Decode layout chosen by the autotuner for this code and path, if any.
+bool tuned_launch(const Sched &sc, int path, DecodeLaunch *out);
+void set_tuned_launch(const Sched &sc, int path, const DecodeLaunch &lc);
+void tune_cache_clear();
+// Times candidate layouts of the specialised kernel (jit) on F zero frames.
+int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStream_t stream, DecodeLaunch *best,
+                    float *best_ms);
 
 }  // namespace ldpc

@@ -192,6 +192,28 @@ def test_int8_wimax(cls, Z):
     _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=10, offset=1, early_term=True))
 
 
+@pytest.mark.parametrize("rate", ["1/2", "5/6"])
+def test_autotuned_layouts_stay_exact(rate):
+    # The autotuner may pick any layout (frames per workgroup and thread,
+    # register variant); results must not change.
+    h = synth.wifi_code(rate, 81)
+    _, _, llr = _frames(h, 81, 211, 1.5, 17)
+    q = oracle.quantize_i8(llr)
+    try:
+        for path in ("f32", "i8"):
+            cfg = P.ldpc_autotune_decode(h, 81, path=path, max_iter=10, F=2048)
+            assert cfg["G"] >= 1 and cfg["KF"] >= 1 and cfg["ms"] > 0
+        got = P.ldpc_decode_f32(h, 81, _gpu(llr), max_iter=10, early_term=True)
+        torch.cuda.synchronize()
+        gp, wp = _assert_f32_parity(got, oracle.decode_f32(h, 81, llr, max_iter=10, early_term=True))
+        assert np.array_equal(gp, wp)
+        got = P.ldpc_decode_i8(h, 81, _gpu(q), max_iter=10, offset=1, early_term=True)
+        torch.cuda.synchronize()
+        _assert_exact(got, oracle.decode_i8(h, 81, q, max_iter=10, offset=1, early_term=True))
+    finally:
+        P.ldpc_cache_clear()
+
+
 # ------------------------------------------------------- full-size, sampled
 
 @pytest.mark.parametrize("rate", list(synth.WIFI_RATES))
