@@ -131,6 +131,34 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
                          int32_t out[5], float *ms, void *stream);
 
 /*
+ * Learned normalised min-sum (training). Weights w[T][Mb][Nb] (device f32)
+ * replace the fixed normalisation: in iteration t (0-based) the message
+ * leaving block column j of block row i is sgn * fl(w[t][i][j] * min), in the
+ * layered schedule of Sec. 4 with early termination off. The loss is binary
+ * cross-entropy of sigmoid(L) (probability of bit 0, eq. 17) against the
+ * transmitted codeword after every iteration:
+ *   loss[t] = 1/(T F N) sum_f sum_n softplus(-(1 - 2 cw[f][n]) L_fn after iteration t),
+ * so that sum_t loss[t] is the mean per-bit, per-iteration BCE.
+ *
+ * ldpc_nms_ckpt_bytes: size of the checkpoint buffer for F frames and T
+ *   iterations (0 on invalid arguments); the caller allocates it on the device.
+ * ldpc_nms_fwd: runs the T iterations on llr (device f32 [F][N]) with target
+ *   cw (device u8 [F][N]); writes per-iteration checkpoints into ckpt, loss
+ *   (device f32 [T]) and optionally the final posteriors post ([F][N]).
+ * ldpc_nms_bwd: hand-written adjoint. From the checkpoints of a forward call
+ *   with the same arguments and dloss (device f32 [T], the gradient of the
+ *   objective with respect to each loss[t]) computes grad_w (device f32
+ *   [T][Mb][Nb], overwritten). Entries of w at zero blocks (-1 in H_bm) get a
+ *   zero gradient. Iterations are recomputed from their checkpoints.
+ * Both need run-time specialisation (LDPC_ERANGE if LDPC_JIT=0).
+ */
+size_t ldpc_nms_ckpt_bytes(const int16_t *hbm, int Mb, int Nb, int Z, int64_t F, int T);
+int ldpc_nms_fwd(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, const uint8_t *cw, int64_t F, int T,
+                 const float *w, void *ckpt, size_t ckpt_bytes, float *loss, float *post, void *stream);
+int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, int64_t F, int T, const float *w,
+                 const void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream);
+
+/*
  * Seeded information bits from Philox4x32-10 (Salmon et al., SC'11):
  * bit k of frame f is bit (k mod 32) of word (k/32 mod 4) of
  * Philox(counter = {k/128, f, 0, 0}, key = {seed low, seed high}).

@@ -17,7 +17,8 @@ import numpy as np
 
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
-    "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
+    "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -37,6 +38,9 @@ EXPORTS = {
     "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p], _i32),
     "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
     "ldpc_autotune_decode": ([_p, _i32, _i32, _i32, _i32, _i32, _i64, _p, _p, _p], _i32),
+    "ldpc_nms_ckpt_bytes": ([_p, _i32, _i32, _i32, _i64, _i32], C.c_size_t),
+    "ldpc_nms_fwd": ([_p, _i32, _i32, _i32, _p, _p, _i64, _i32, _p, _p, C.c_size_t, _p, _p, _p], _i32),
+    "ldpc_nms_bwd": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _p, _p, C.c_size_t, _p, _p, _p], _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -226,3 +230,48 @@ def ldpc_awgn_llr(seed, cw, sigma, scale, out=None, stream=None):
     _check(lib().ldpc_awgn_llr(int(seed), _dev(cw, torch.uint8, "cw", (F, N)), F, N, float(sigma), float(scale),
                                _dev(out, torch.float32, "llr", (F, N)), _stream(stream)), "ldpc_awgn_llr")
     return out
+
+
+def ldpc_nms_ckpt_bytes(hbm, Z, F, T):
+    h = _hbm(hbm)
+    n = lib().ldpc_nms_ckpt_bytes(_hptr(h), h.shape[0], h.shape[1], Z, int(F), int(T))
+    if n == 0:
+        raise LdpcError(LDPC_EINVAL, "ldpc_nms_ckpt_bytes", "invalid code or sizes")
+    return int(n)
+
+
+def ldpc_nms_fwd(hbm, Z, llr, cw, w, ckpt=None, post=None, want_post=False, stream=None):
+    """Training forward of the learned decoder (T = w.shape[0] iterations).
+    Returns (loss [T] f32 on the device, checkpoint buffer u8, post or None)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    T = w.shape[0]
+    nbytes = ldpc_nms_ckpt_bytes(h, Z, F, T)
+    if ckpt is None:
+        ckpt = torch.empty(nbytes, dtype=torch.uint8, device=llr.device)
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.float32, device=llr.device)
+    loss = torch.empty(T, dtype=torch.float32, device=llr.device)
+    _check(lib().ldpc_nms_fwd(_hptr(h), Mb, Nb, Z, _dev(llr, torch.float32, "llr", (F, Nb * Z)),
+                              _dev(cw, torch.uint8, "cw", (F, N)), F, T, _dev(w, torch.float32, "w", (T, Mb, Nb)),
+                              _dev(ckpt, torch.uint8, "ckpt"), ckpt.numel(), _dev(loss, torch.float32, "loss"),
+                              _opt(post, torch.float32, "post", (F, N)), _stream(stream)), "ldpc_nms_fwd")
+    return loss, ckpt, post
+
+
+def ldpc_nms_bwd(hbm, Z, cw, w, ckpt, dloss, grad_w=None, stream=None):
+    """Adjoint of ldpc_nms_fwd: gradient of sum_t dloss[t] * loss[t] w.r.t. w."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = cw.shape
+    T = w.shape[0]
+    if grad_w is None:
+        grad_w = torch.empty((T, Mb, Nb), dtype=torch.float32, device=cw.device)
+    _check(lib().ldpc_nms_bwd(_hptr(h), Mb, Nb, Z, _dev(cw, torch.uint8, "cw", (F, N)), F, T,
+                              _dev(w, torch.float32, "w", (T, Mb, Nb)), _dev(ckpt, torch.uint8, "ckpt"), ckpt.numel(),
+                              _dev(dloss, torch.float32, "dloss", (T,)),
+                              _dev(grad_w, torch.float32, "grad_w", (T, Mb, Nb)), _stream(stream)), "ldpc_nms_bwd")
+    return grad_w

@@ -23,17 +23,23 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 GPU = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+JIT_SOURCES = [("jit_decode.hip", "kJitDecodeSource"), ("jit_nms.hip", "kJitNmsSource")]
+
+
 def _embed_jit_source():
-    """Writes _build/jit_source.cpp: jit_decode.hip as a C++ string for hipRTC."""
-    with open(os.path.join(CSRC, "jit_decode.hip")) as fh:
-        text = fh.read()
+    """Writes _build/jit_source.cpp: the hipRTC kernel sources as C++ strings."""
     delim = "LDPCJIT"
-    assert ")" + delim not in text
     out = os.path.join(OBJ, "jit_source.cpp")
+    parts = ["// generated from csrc/jit_*.hip by build.py", "namespace ldpc {"]
+    for fname, sym in JIT_SOURCES:
+        with open(os.path.join(CSRC, fname)) as fh:
+            text = fh.read()
+        assert ")" + delim not in text
+        parts.append(f"extern const char {sym}[];")
+        parts.append(f"const char {sym}[] = R\"{delim}(\n{text}){delim}\";")
+    parts.append("}")
     with open(out, "w") as fh:
-        fh.write("// generated from csrc/jit_decode.hip by build.py\n"
-                 "namespace ldpc {\nextern const char kJitDecodeSource[];\n"
-                 f"const char kJitDecodeSource[] = R\"{delim}(\n{text}){delim}\";\n}}\n")
+        fh.write("\n".join(parts) + "\n")
     return out
 
 

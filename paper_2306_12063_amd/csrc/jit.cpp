@@ -19,14 +19,14 @@
 
 namespace ldpc {
 
-// Kernel source, embedded at build time from jit_decode.hip.
+// Kernel sources, embedded at build time from jit_decode.hip and jit_nms.hip.
 extern const char kJitDecodeSource[];
+extern const char kJitNmsSource[];
 
 namespace {
 
 struct JitKernel {
     hipModule_t mod = nullptr;
-    hipFunction_t fn = nullptr;
 };
 
 std::mutex g_mu;
@@ -89,27 +89,21 @@ int load(const std::string &code, JitKernel *out)
     hipModule_t mod;
     if (hipModuleLoadData(&mod, code.data()) != hipSuccess)
         return fail(LDPC_EDEVICE, "hipModuleLoadData failed: %s", hipGetErrorString(hipGetLastError()));
-    hipFunction_t fn;
-    if (hipModuleGetFunction(&fn, mod, "ldpc_jit_decode") != hipSuccess) {
-        hipModuleUnload(mod);
-        return fail(LDPC_EDEVICE, "hipModuleGetFunction failed");
-    }
     out->mod = mod;
-    out->fn = fn;
     return LDPC_OK;
 }
 
-int get_kernel(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn)
+// Module for (device, source, prelude), compiled on first use.
+int get_module(const char *tag, const char *src, const std::string &pre, hipModule_t *mod)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return fail(LDPC_EDEVICE, "hipGetDevice failed");
-    const std::string pre = prelude(sc, lc, path, mode);
-    const std::string key = std::to_string(dev) + "\n" + pre;
+    const std::string key = std::to_string(dev) + "\n" + tag + "\n" + pre;
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
-        *fn = it->second.fn;
+        *mod = it->second.mod;
         return LDPC_OK;
     }
     hipDeviceProp_t prop;
@@ -120,14 +114,32 @@ int get_kernel(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipF
     if (colon != std::string::npos)
         arch = arch.substr(0, colon);
     std::string code;
-    int rc = rtc_compile(pre + kJitDecodeSource, arch, &code);
+    int rc = rtc_compile(pre + src, arch, &code);
     if (rc)
         return rc;
     JitKernel k;
     if ((rc = load(code, &k)))
         return rc;
     g_cache.emplace(key, k);
-    *fn = k.fn;
+    *mod = k.mod;
+    return LDPC_OK;
+}
+
+int get_function(const char *tag, const char *src, const std::string &pre, const char *name, hipFunction_t *fn)
+{
+    hipModule_t mod;
+    int rc = get_module(tag, src, pre, &mod);
+    if (rc)
+        return rc;
+    if (hipModuleGetFunction(fn, mod, name) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipModuleGetFunction(%s) failed", name);
+    return LDPC_OK;
+}
+
+int launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what)
+{
+    if (hipModuleLaunchKernel(fn, blocks, 1, 1, threads, 1, 1, 0, stream, args, nullptr) != hipSuccess)
+        return fail(LDPC_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(hipGetLastError()));
     return LDPC_OK;
 }
 
@@ -152,16 +164,84 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream)
 {
     hipFunction_t fn;
-    int rc = get_kernel(sc, lc, path, mode, &fn);
+    int rc = get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode), "ldpc_jit_decode", &fn);
     if (rc)
         return rc;
     long long Fll = (long long)F;
     void *args[] = {(void *)&llr, (void *)&fidx, (void *)&Fll, (void *)&max_iter, (void *)&alpha, (void *)&offset,
                     (void *)&wq, (void *)&et, (void *)&wt, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
-    const unsigned blocks = (unsigned)((F + lc.FW - 1) / lc.FW);
-    if (hipModuleLaunchKernel(fn, blocks, 1, 1, lc.threads, 1, 1, 0, stream, args, nullptr) != hipSuccess)
-        return fail(LDPC_EDEVICE, "decode launch failed: %s", hipGetErrorString(hipGetLastError()));
-    return LDPC_OK;
+    return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "decode");
+}
+
+// ---------------------------------------------------------------------------
+// Learned normalised min-sum (jit_nms.hip)
+// ---------------------------------------------------------------------------
+
+DecodeLaunch plan_nms(const Sched &sc)
+{
+    // one frame per thread group; the adjoint keeps L and gL (FP32) for the
+    // workgroup's frames in LDS, frame-minor with an odd row stride
+    DecodeLaunch best{};
+    double best_util = -1.0;
+    for (int G = 1; G * sc.Z <= kMaxThreads && G <= 64; ++G) {
+        const int FWp = G | 1;
+        const size_t lds = 2 * (size_t)sc.N * FWp * sizeof(float);
+        if (lds > (size_t)kLdsBudget)
+            break;
+        const int threads = ((G * sc.Z + 63) / 64) * 64;
+        const double util = (double)(G * sc.Z) / threads;
+        if (util > best_util + 1e-9) {
+            best_util = util;
+            best = DecodeLaunch{G, 1, G, FWp, threads, lds, 1};
+        }
+    }
+    return best;
+}
+
+size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T)
+{
+    return (size_t)T * (size_t)F * ((size_t)sc.N + 3 * (size_t)sc.M) + (size_t)T * (size_t)F;
+}
+
+int launch_nms_fwd(const Sched &sc, const float *llr, const uint8_t *cw, int64_t F, int T, const float *w,
+                   float *ckpt, float *loss, float *post, hipStream_t stream)
+{
+    const DecodeLaunch lc = plan_nms(sc);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the training kernels' LDS budget", sc.N);
+    const std::string pre = prelude(sc, lc, 0, 1);
+    hipFunction_t fwd, red;
+    int rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_fwd", &fwd);
+    if (rc || (rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_loss_reduce", &red)))
+        return rc;
+    float *loss_tf = ckpt + (size_t)T * (size_t)F * ((size_t)sc.N + 3 * (size_t)sc.M);
+    long long Fll = (long long)F;
+    void *a1[] = {(void *)&llr, (void *)&cw, (void *)&Fll, (void *)&T, (void *)&w, (void *)&ckpt, (void *)&loss_tf,
+                  (void *)&post};
+    if ((rc = launch(fwd, (unsigned)((F + lc.G - 1) / lc.G), lc.threads, stream, a1, "nms forward")))
+        return rc;
+    void *a2[] = {(void *)&loss_tf, (void *)&Fll, (void *)&T, (void *)&loss};
+    return launch(red, (unsigned)T, 256, stream, a2, "nms loss");
+}
+
+int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, const float *ckpt,
+                   const float *dloss, float *grad_w, hipStream_t stream)
+{
+    const DecodeLaunch lc = plan_nms(sc);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the training kernels' LDS budget", sc.N);
+    const std::string pre = prelude(sc, lc, 0, 1);
+    hipFunction_t bwd, zero;
+    int rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_bwd", &bwd);
+    if (rc || (rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_zero", &zero)))
+        return rc;
+    long long nw = (long long)T * sc.Mb * sc.Nb;
+    void *az[] = {(void *)&grad_w, (void *)&nw};
+    if ((rc = launch(zero, (unsigned)((nw + 255) / 256), 256, stream, az, "nms zero")))
+        return rc;
+    long long Fll = (long long)F;
+    void *a[] = {(void *)&cw, (void *)&Fll, (void *)&T, (void *)&w, (void *)&ckpt, (void *)&dloss, (void *)&grad_w};
+    return launch(bwd, (unsigned)((F + lc.G - 1) / lc.G), lc.threads, stream, a, "nms adjoint");
 }
 
 }  // namespace ldpc

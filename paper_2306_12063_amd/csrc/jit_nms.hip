@@ -1,0 +1,369 @@
+// Learned normalised min-sum: training forward with per-iteration
+// checkpoints and loss, and its hand-written adjoint, specialised for one
+// code at run time (hipRTC, same prelude as jit_decode.hip; LDPC_KF is 1).
+//
+// Model. Weights w[T][MB][NB] scale the messages: in iteration t (0-based)
+// the message leaving edge e of a check row of block row i is
+//   R_e = sgn_e * fl(w[t][i][col_e] * m_e),
+// m_e = min over the other edges of |Q|, sgn_e = product of their signs,
+// Q_e = L[n_e] - R_old_e (eq. 22) with R_old_e the message of iteration t-1,
+// and L[n_e] = Q_e + R_e (eq. 20), in the layered order of Sec. 4. The loss
+// is l = 1/(T F N) sum_t sum_f sum_n softplus(-(1 - 2 c_fn) L_fn^(t)), the
+// binary cross-entropy of sigmoid(L) (the probability of bit 0, eq. 17)
+// after every iteration. Early termination is off.
+//
+// Checkpoint of iteration t (taken when it starts), per frame: L (N FP32)
+// and the compressed row state (raw minima m1, m2 and sign/argmin word,
+// one triple per check row). The adjoint restores it, recomputes the
+// iteration keeping each row's Q values in registers, then runs the layers
+// in reverse:
+//   G_e = gL[n_e] + gR_e                      (R_e feeds L and the next Q)
+//   gw[t][i][col_e] += G_e * sgn_e * m_e
+//   gm_e = G_e * sgn_e * w[t][i][col_e]
+//   g|Q|_a1 += sum_{e != a1} gm_e,  g|Q|_a2 += gm_a1   (a1, a2: first and second
+//                                                       smallest |Q|, lowest index first)
+//   gQ_e = gL[n_e] + g|Q|_e * sgn(Q_e);  gL[n_e] = gQ_e;  gR_e = -gQ_e
+// and before the layers of iteration t adds d l / d L^(t+1) to gL.
+
+typedef unsigned char u8;
+typedef unsigned int u32;
+typedef long long i64;
+
+constexpr int Z = LDPC_Z, MB = LDPC_MB, NB = LDPC_NB, N = LDPC_N, MAXD = LDPC_MAXD;
+constexpr int G = LDPC_G, FWP = LDPC_FWP;
+constexpr int M = MB * Z;
+constexpr int ZFW = Z * FWP;
+
+// edges of a check row over all block rows, and the offset of block row i
+constexpr int row_edges()
+{
+    int s = 0;
+    for (int i = 0; i < MB; ++i)
+        s += kDeg[i];
+    return s;
+}
+constexpr int edge_off(int i)
+{
+    int s = 0;
+    for (int k = 0; k < i; ++k)
+        s += kDeg[k];
+    return s;
+}
+constexpr int ED = row_edges();
+
+__device__ __forceinline__ int gather(int i, int e, int r, int rb)
+{
+    const int base = (kCol[i][e] * Z + kShift[i][e]) * FWP;
+    return rb + base - ((r >= Z - kShift[i][e]) ? ZFW : 0);
+}
+
+__device__ __forceinline__ float softplus(float z) { return __builtin_fmaxf(z, 0.0f) + log1pf(expf(-__builtin_fabsf(z))); }
+
+__device__ __forceinline__ float sigmoid(float z)
+{
+    if (z >= 0.0f)
+        return 1.0f / (1.0f + expf(-z));
+    const float e = expf(z);
+    return e / (1.0f + e);
+}
+
+// Checkpoint layout for iteration t and frame f (all FP32 words):
+//   L      at ((t*F + f) * CK)             N values
+//   m1, m2 at ((t*F + f) * CK) + N, + N + M  M values each (row i*Z + r)
+//   sg     at ((t*F + f) * CK) + N + 2M    M words
+constexpr int CK = N + 3 * M;
+
+// One layer of the forward for the thread's check row. Writes new L values
+// to LDS and the new compressed state; if QS is given, stores the row's Q
+// values there (backward recompute).
+__device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls, const float *__restrict__ w,
+                                          float &m1s, float &m2s, u32 &sgs, float *QS)
+{
+    const int d = kDeg[i];
+    int ix[MAXD];
+    float Q[MAXD];
+#pragma unroll
+    for (int e = 0; e < MAXD; ++e)
+        if (e < d)
+            ix[e] = gather(i, e, r, rb);
+    const u32 oidx = sgs >> 27;
+#pragma unroll
+    for (int e = 0; e < MAXD; ++e) {
+        if (e >= d)
+            continue;
+        // old message: raw minimum times the weight of the iteration that made it
+        const float m = (oidx == (u32)e) ? m2s : m1s;
+        const float mag = t > 0 ? w[((t - 1) * MB + i) * NB + kCol[i][e]] * m : 0.0f;
+        const u32 ro = __float_as_uint(mag) | ((sgs << (32 - d + e)) & 0x80000000u);
+        Q[e] = Ls[ix[e]] - __uint_as_float(ro);
+    }
+    u32 idx = 0, neg = 0;
+    float m1 = __builtin_inff(), m2 = __builtin_inff();
+#pragma unroll
+    for (int e = 0; e < MAXD; ++e) {
+        if (e >= d)
+            continue;
+        const float a = __builtin_fabsf(Q[e]);
+        idx = (a < m1) ? (u32)e : idx;
+        m2 = __builtin_amdgcn_fmed3f(a, m1, m2);
+        m1 = __builtin_fminf(m1, a);
+        neg = __builtin_amdgcn_alignbit(neg, __float_as_uint(Q[e]), 31);
+    }
+    const u32 par = (u32)__popc(neg) & 1u;
+    const u32 parbit = par << 31;
+#pragma unroll
+    for (int e = 0; e < MAXD; ++e) {
+        if (e >= d)
+            continue;
+        const float mag = w[(t * MB + i) * NB + kCol[i][e]] * ((idx == (u32)e) ? m2 : m1);
+        const u32 rn = __float_as_uint(mag) | ((__float_as_uint(Q[e]) ^ parbit) & 0x80000000u);
+        Ls[ix[e]] = Q[e] + __uint_as_float(rn);
+        if (QS)
+            QS[e] = Q[e];
+    }
+    m1s = m1;
+    m2s = m2;
+    sgs = (neg ^ ((0u - par) & ((1u << d) - 1u))) | (idx << 27);
+}
+
+extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
+    const float *__restrict__ llr, const u8 *__restrict__ cw, const i64 F, const int T, const float *__restrict__ w,
+    float *__restrict__ ckpt, float *__restrict__ loss_tf, float *__restrict__ post)
+{
+    __shared__ float Ls[N * FWP];
+    __shared__ float part[G * Z];
+    const int tid = threadIdx.x;
+    const int g = tid / Z;
+    const int r = tid - g * Z;
+    const i64 f = (i64)blockIdx.x * G + g;
+    const bool on = g < G && f < F;
+    const int rb = r * FWP + g;
+    for (int s = 0; s < G; ++s) {
+        const i64 fs = (i64)blockIdx.x * G + s;
+        if (fs >= F)
+            break;
+        for (int n = tid; n < N; n += LDPC_THREADS)
+            Ls[n * FWP + s] = llr[fs * N + n] + 0.0f;
+    }
+    float sm1[MB], sm2[MB];
+    u32 ssg[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        sm1[i] = 0.0f;
+        sm2[i] = 0.0f;
+        ssg[i] = 0u;
+    }
+    __syncthreads();
+    for (int t = 0; t < T; ++t) {
+        if (on) {
+            float *ck = ckpt + ((i64)t * F + f) * CK;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                ck[j * Z + r] = Ls[(j * Z + r) * FWP + g];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                ck[N + i * Z + r] = sm1[i];
+                ck[N + M + i * Z + r] = sm2[i];
+                ck[N + 2 * M + i * Z + r] = __uint_as_float(ssg[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            if (on)
+                fwd_layer(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], nullptr);
+            __syncthreads();
+        }
+        // per-frame loss of this iteration: thread r sums variables j*Z + r
+        float acc = 0.0f;
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int n = j * Z + r;
+                const float x = cw[f * N + n] ? -1.0f : 1.0f;
+                acc += softplus(-x * Ls[n * FWP + g]);
+            }
+        }
+        if (g < G)
+            part[g * Z + r] = acc;
+        __syncthreads();
+        if (on && r == 0) {
+            float s = 0.0f;
+            for (int k = 0; k < Z; ++k)
+                s += part[g * Z + k];
+            loss_tf[(i64)t * F + f] = s;
+        }
+        __syncthreads();
+    }
+    if (post && on) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            post[f * N + j * Z + r] = Ls[(j * Z + r) * FWP + g];
+    }
+}
+
+// loss[t] = (1 / (T F N)) sum_f loss_tf[t][f], one workgroup per iteration,
+// summed in a fixed order.
+extern "C" __global__ __launch_bounds__(256) void ldpc_nms_loss_reduce(const float *__restrict__ loss_tf, const i64 F,
+                                                                      const int T, float *__restrict__ loss)
+{
+    __shared__ double red[256];
+    const int t = blockIdx.x;
+    double s = 0.0;
+    for (i64 f = threadIdx.x; f < F; f += 256)
+        s += (double)loss_tf[(i64)t * F + f];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k)
+            red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        loss[t] = (float)(red[0] / ((double)T * (double)F * (double)N));
+}
+
+extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
+    const u8 *__restrict__ cw, const i64 F, const int T, const float *__restrict__ w,
+    const float *__restrict__ ckpt, const float *__restrict__ dloss, float *__restrict__ grad_w)
+{
+    __shared__ float Ls[N * FWP];
+    __shared__ float gL[N * FWP];
+    __shared__ float gw[MB * NB];
+    const int tid = threadIdx.x;
+    const int g = tid / Z;
+    const int r = tid - g * Z;
+    const i64 f = (i64)blockIdx.x * G + g;
+    const bool on = g < G && f < F;
+    const int rb = r * FWP + g;
+    const double inv = 1.0 / ((double)T * (double)F * (double)N);
+    float gR[ED];
+    float QS[ED];
+#pragma unroll
+    for (int k = 0; k < ED; ++k)
+        gR[k] = 0.0f;
+    for (int n = tid; n < N * FWP; n += LDPC_THREADS)
+        gL[n] = 0.0f;
+    for (int k = tid; k < MB * NB; k += LDPC_THREADS)
+        gw[k] = 0.0f;
+    __syncthreads();
+    for (int t = T - 1; t >= 0; --t) {
+        // restore the start of iteration t and recompute it, keeping Q
+        float sm1[MB], sm2[MB];
+        u32 ssg[MB];
+        if (on) {
+            const float *ck = ckpt + ((i64)t * F + f) * CK;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                Ls[(j * Z + r) * FWP + g] = ck[j * Z + r];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                sm1[i] = ck[N + i * Z + r];
+                sm2[i] = ck[N + M + i * Z + r];
+                ssg[i] = __float_as_uint(ck[N + 2 * M + i * Z + r]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            if (on)
+                fwd_layer(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], QS + edge_off(i));
+            __syncthreads();
+        }
+        // the loss reads L after iteration t directly
+        const float sc = (float)((double)dloss[t] * inv);
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int n = j * Z + r;
+                const float x = cw[f * N + n] ? -1.0f : 1.0f;
+                gL[n * FWP + g] += -x * sigmoid(-x * Ls[n * FWP + g]) * sc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < MB; ++ii) {
+            const int i = MB - 1 - ii;
+            const int d = kDeg[i];
+            if (on) {
+                const float *Q = QS + edge_off(i);
+                float *gr = gR + edge_off(i);
+                int ix[MAXD];
+#pragma unroll
+                for (int e = 0; e < MAXD; ++e)
+                    if (e < d)
+                        ix[e] = gather(i, e, r, rb);
+                // first and second smallest |Q| (values v1, v2 at a1, a2),
+                // lowest index first
+                int a1 = 0, a2 = 1;
+                float v1 = __builtin_fabsf(Q[0]), v2 = __builtin_fabsf(Q[1]);
+                if (v2 < v1) {
+                    a1 = 1;
+                    a2 = 0;
+                    const float tmp = v1;
+                    v1 = v2;
+                    v2 = tmp;
+                }
+                u32 neg = (__float_as_uint(Q[0]) >> 31) ^ (__float_as_uint(Q[1]) >> 31);
+#pragma unroll
+                for (int e = 2; e < MAXD; ++e) {
+                    if (e >= d)
+                        continue;
+                    const float a = __builtin_fabsf(Q[e]);
+                    if (a < v1) {
+                        a2 = a1;
+                        v2 = v1;
+                        a1 = e;
+                        v1 = a;
+                    } else if (a < v2) {
+                        a2 = e;
+                        v2 = a;
+                    }
+                    neg ^= __float_as_uint(Q[e]) >> 31;
+                }
+                float gQ1 = 0.0f, gQ2 = 0.0f, gl[MAXD];
+#pragma unroll
+                for (int e = 0; e < MAXD; ++e) {
+                    if (e >= d)
+                        continue;
+                    gl[e] = gL[ix[e]];
+                    const float sg = ((neg ^ (__float_as_uint(Q[e]) >> 31)) & 1u) ? -1.0f : 1.0f;
+                    const float m = (e == a1) ? v2 : v1;
+                    const float Ge = gl[e] + gr[e];
+                    const float wv = w[(t * MB + i) * NB + kCol[i][e]];
+                    atomicAdd(&gw[i * NB + kCol[i][e]], Ge * sg * m);
+                    const float gm = Ge * sg * wv;
+                    if (e == a1)
+                        gQ2 += gm;
+                    else
+                        gQ1 += gm;
+                }
+#pragma unroll
+                for (int e = 0; e < MAXD; ++e) {
+                    if (e >= d)
+                        continue;
+                    const float ga = (e == a1) ? gQ1 : ((e == a2) ? gQ2 : 0.0f);
+                    const float sq = Q[e] < 0.0f ? -1.0f : 1.0f;
+                    const float gq = gl[e] + ga * sq;
+                    gL[ix[e]] = gq;
+                    gr[e] = -gq;
+                }
+            }
+            __syncthreads();
+        }
+        // this iteration's weight gradient: one atomic per weight and workgroup
+        for (int k = tid; k < MB * NB; k += LDPC_THREADS) {
+            const float v = gw[k];
+            if (v != 0.0f)
+                atomicAdd(&grad_w[t * MB * NB + k], v);
+            gw[k] = 0.0f;
+        }
+        __syncthreads();
+    }
+}
+
+extern "C" __global__ void ldpc_nms_zero(float *__restrict__ p, const i64 n)
+{
+    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n)
+        p[k] = 0.0f;
+}

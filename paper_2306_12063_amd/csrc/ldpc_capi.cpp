@@ -324,6 +324,54 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
     return LDPC_OK;
 }
 
+size_t ldpc_nms_ckpt_bytes(const int16_t *hbm, int Mb, int Nb, int Z, int64_t F, int T)
+{
+    clear_error();
+    Sched sc;
+    if (compile_sched(hbm, Mb, Nb, Z, true, &sc) || F < 0 || T < 1)
+        return 0;
+    return nms_ckpt_floats(sc, F, T) * sizeof(float);
+}
+
+int ldpc_nms_fwd(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, const uint8_t *cw, int64_t F, int T,
+                 const float *w, void *ckpt, size_t ckpt_bytes, float *loss, float *post, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if (F < 1 || T < 1)
+        return fail(LDPC_EINVAL, "F and T must be >= 1");
+    if (bad_ptrs({llr, cw, w, ckpt, loss}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, cw, w, ckpt and loss are required)");
+    if (ckpt_bytes < nms_ckpt_floats(sc, F, T) * sizeof(float))
+        return fail(LDPC_EINVAL, "checkpoint buffer too small: %zu < %zu bytes", ckpt_bytes,
+                    nms_ckpt_floats(sc, F, T) * sizeof(float));
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the training kernels need run-time specialisation (LDPC_JIT=0 is set)");
+    return launch_nms_fwd(sc, llr, cw, F, T, w, (float *)ckpt, loss, post, (hipStream_t)stream);
+}
+
+int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, int64_t F, int T, const float *w,
+                 const void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if (F < 1 || T < 1)
+        return fail(LDPC_EINVAL, "F and T must be >= 1");
+    if (bad_ptrs({cw, w, ckpt, dloss, grad_w}))
+        return fail(LDPC_EINVAL, "null device pointer (cw, w, ckpt, dloss and grad_w are required)");
+    if (ckpt_bytes < nms_ckpt_floats(sc, F, T) * sizeof(float))
+        return fail(LDPC_EINVAL, "checkpoint buffer too small");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the training kernels need run-time specialisation (LDPC_JIT=0 is set)");
+    return launch_nms_bwd(sc, cw, F, T, w, (const float *)ckpt, dloss, grad_w, (hipStream_t)stream);
+}
+
 int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream)
 {
     clear_error();

@@ -77,6 +77,13 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
 
+// Learned normalised min-sum training kernels (jit.cpp, jit_nms.hip).
+size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T);
+int launch_nms_fwd(const Sched &sc, const float *llr, const uint8_t *cw, int64_t F, int T, const float *w,
+                   float *ckpt, float *loss, float *post, hipStream_t stream);
+int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, const float *ckpt,
+                   const float *dloss, float *grad_w, hipStream_t stream);
+
 // Picks G/KF for a code and element size (4 for FP32, 2 for int16 posteriors).
 DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint);
 // Layout for a given G and KF (G < 1 in the result if it does not fit).
