@@ -174,9 +174,37 @@ int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *s
  * words (2p, 2p+1) with p = (n mod 4)/2 give u = ((word >> 8) + 1/2) 2^-24,
  * z = sqrt(-2 ln u_a) * (cos for even n, sin for odd n)(2 pi u_b).
  *   cw  : device u8 [F][N] codeword bits,  llr : device f32 [F][N]
+ *   sigma_f, scale_f : nullable device f32 [F]; when given (both), frame f
+ *         uses sigma_f[f] and scale_f[f] instead of sigma and scale
  */
-int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale, float *llr,
-                  void *stream);
+int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale,
+                  const float *sigma_f, const float *scale_f, float *llr, void *stream);
+
+/*
+ * Decoding statistics against the transmitted information bits (the first K
+ * bits of each codeword, eq. 1). Adds to counters (device int64 [4], not
+ * cleared): [0] information-bit errors, [1] frames with any such error,
+ * [2] iterations (if iters is given), [3] frames with ok == 0 (if ok is
+ * given). bits: device u8 [F][N]; info: device u8 [F][K].
+ */
+int ldpc_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
+                     int64_t N, int64_t K, int64_t *counters, void *stream);
+
+/*
+ * Fallback: the frames whose ok flag is 0 after a decode are decoded again
+ * from their channel LLRs with fresh state by plain min-sum (FP32 weight
+ * alpha; int8 offset or wq/16 as for ldpc_decode_i8) with early termination
+ * and at most max_iter iterations; their bits, posteriors (if post is given),
+ * iteration counts and ok flags are overwritten, the other frames are left
+ * as they are. work: device int64 [F + 1] scratch (receives the count and
+ * the list of re-decoded frames, in frame order). The list length stays on
+ * the device: no host synchronisation.
+ */
+int ldpc_fallback_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                      float alpha, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok, int64_t *work,
+                      void *stream);
+int ldpc_fallback_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter, int offset,
+                     int wq, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, int64_t *work, void *stream);
 
 /*
  * int8 quantiser for channel LLRs: q = clamp(rint(scale * llr), -127, 127),

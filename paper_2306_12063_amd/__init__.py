@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
-    "ldpc_random_bits", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -35,7 +35,10 @@ EXPORTS = {
     "ldpc_decode_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_random_bits": ([_u64, _i64, _i64, _p, _p], _i32),
-    "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p], _i32),
+    "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p, _p, _p], _i32),
+    "ldpc_frame_stats": ([_p, _p, _p, _p, _i64, _i64, _i64, _p, _p], _i32),
+    "ldpc_fallback_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _p, _p, _p, _p, _p, _p], _i32),
+    "ldpc_fallback_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
     "ldpc_autotune_decode": ([_p, _i32, _i32, _i32, _i32, _i32, _i64, _p, _p, _p], _i32),
     "ldpc_nms_ckpt_bytes": ([_p, _i32, _i32, _i32, _i64, _i32], C.c_size_t),
@@ -224,12 +227,66 @@ def ldpc_random_bits(seed, F, K, out=None, device="cuda", stream=None):
 
 
 def ldpc_awgn_llr(seed, cw, sigma, scale, out=None, stream=None):
+    """BPSK/AWGN channel LLRs for codewords cw [F][N]. sigma and scale are
+    floats, or GPU float32 tensors [F] of per-frame values."""
     torch = _torch()
     F, N = cw.shape
     out = torch.empty((F, N), dtype=torch.float32, device=cw.device) if out is None else out
+    sf = cf = None
+    if isinstance(sigma, torch.Tensor):
+        sf, cf = _dev(sigma, torch.float32, "sigma", (F,)), _dev(scale, torch.float32, "scale", (F,))
+        sigma = scale = 0.0
     _check(lib().ldpc_awgn_llr(int(seed), _dev(cw, torch.uint8, "cw", (F, N)), F, N, float(sigma), float(scale),
-                               _dev(out, torch.float32, "llr", (F, N)), _stream(stream)), "ldpc_awgn_llr")
+                               sf, cf, _dev(out, torch.float32, "llr", (F, N)), _stream(stream)), "ldpc_awgn_llr")
     return out
+
+
+def ldpc_frame_stats(bits, info, iters=None, ok=None, counters=None, stream=None):
+    """Adds (info-bit errors, frame errors, iterations, failed syndromes) of a
+    decoded batch to int64 device counters [4]; returns the counters."""
+    torch = _torch()
+    F, N = bits.shape
+    K = info.shape[1]
+    if counters is None:
+        counters = torch.zeros(4, dtype=torch.int64, device=bits.device)
+    _check(lib().ldpc_frame_stats(_dev(bits, torch.uint8, "bits", (F, N)), _dev(info, torch.uint8, "info", (F, K)),
+                                  _opt(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)), F, N, K,
+                                  _dev(counters, torch.int64, "counters", (4,)), _stream(stream)), "ldpc_frame_stats")
+    return counters
+
+
+def _work(F, device):
+    return _torch().empty(F + 1, dtype=_torch().int64, device=device)
+
+
+def ldpc_fallback_f32(hbm, Z, llr, bits, iters, ok, post=None, max_iter=20, alpha=0.75, work=None, stream=None):
+    """Re-decodes frames with ok == 0 by plain FP32 NMS (in place)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    work = _work(F, llr.device) if work is None else work
+    _check(lib().ldpc_fallback_f32(_hptr(h), Mb, Nb, Z, _dev(llr, torch.float32, "llr", (F, Nb * Z)), F,
+                                   int(max_iter), float(alpha), _dev(bits, torch.uint8, "bits", (F, N)),
+                                   _opt(post, torch.float32, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
+                                   _dev(ok, torch.uint8, "ok", (F,)), _dev(work, torch.int64, "work", (F + 1,)),
+                                   _stream(stream)), "ldpc_fallback_f32")
+    return bits, post, iters, ok
+
+
+def ldpc_fallback_i8(hbm, Z, llr, bits, iters, ok, post=None, max_iter=20, offset=0, wq=12, work=None, stream=None):
+    """Re-decodes frames with ok == 0 by plain fixed-point min-sum (in place)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    work = _work(F, llr.device) if work is None else work
+    _check(lib().ldpc_fallback_i8(_hptr(h), Mb, Nb, Z, _dev(llr, torch.int8, "llr", (F, Nb * Z)), F, int(max_iter),
+                                  int(offset), int(wq), _dev(bits, torch.uint8, "bits", (F, N)),
+                                  _opt(post, torch.int16, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
+                                  _dev(ok, torch.uint8, "ok", (F,)), _dev(work, torch.int64, "work", (F + 1,)),
+                                  _stream(stream)), "ldpc_fallback_i8")
+    return bits, post, iters, ok
 
 
 def ldpc_nms_ckpt_bytes(hbm, Z, F, T):

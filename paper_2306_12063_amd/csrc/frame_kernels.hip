@@ -48,7 +48,8 @@ __global__ void k_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *__re
 // cos for even n, sin for odd n. LLR = ((1 - 2x) + sigma z) * scale, in FP32
 // without fused multiply-add. One thread per 4 consecutive positions.
 __global__ void k_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *__restrict__ cw, float sigma,
-                           float scale, float *__restrict__ llr)
+                           float scale, const float *__restrict__ sigma_f, const float *__restrict__ scale_f,
+                           float *__restrict__ llr)
 {
     const int64_t quads = (N + 3) / 4;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,6 +66,10 @@ __global__ void k_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *_
     const float z[4] = {r0 * cosf(two_pi * ub0), r0 * sinf(two_pi * ub0), r1 * cosf(two_pi * ub1),
                         r1 * sinf(two_pi * ub1)};
     const int64_t base = f * N + q * 4;
+    if (sigma_f) {
+        sigma = sigma_f[f];
+        scale = scale_f[f];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (q * 4 + j < N) {
@@ -166,6 +171,67 @@ __global__ __launch_bounds__(kMaxThreads) void k_encode(const Sched sc, const in
     }
 }
 
+// Per-frame decoding statistics against the transmitted information bits
+// (the first K code bits, eq. 1): counters[0] += information-bit errors,
+// [1] += frames with any such error, [2] += iterations, [3] += frames whose
+// syndrome check failed. Integer atomics, so the totals do not depend on
+// the order of the additions. One workgroup per frame.
+__global__ __launch_bounds__(256) void k_frame_stats(const uint8_t *__restrict__ bits, const uint8_t *__restrict__ info,
+                                                     const int32_t *__restrict__ iters, const uint8_t *__restrict__ ok,
+                                                     int64_t N, int64_t K, unsigned long long *__restrict__ counters)
+{
+    __shared__ unsigned int red[256];
+    const int64_t f = blockIdx.x;
+    unsigned int e = 0;
+    for (int64_t k = threadIdx.x; k < K; k += 256)
+        e += (bits[f * N + k] ^ info[f * K + k]) & 1u;
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&counters[0], (unsigned long long)red[0]);
+        atomicAdd(&counters[1], red[0] ? 1ull : 0ull);
+        if (iters)
+            atomicAdd(&counters[2], (unsigned long long)iters[f]);
+        if (ok)
+            atomicAdd(&counters[3], ok[f] ? 0ull : 1ull);
+    }
+}
+
+// Indices of the frames with ok == 0, in frame order: out[0] = count,
+// out[1 .. count] = indices. One workgroup; each thread owns a contiguous
+// chunk of frames and the chunk offsets come from a scan in LDS, so the
+// list is the same on every run.
+__global__ __launch_bounds__(1024) void k_compact_failed(const uint8_t *__restrict__ ok, int64_t F,
+                                                        int64_t *__restrict__ out)
+{
+    __shared__ int64_t cnt[1024];
+    const int64_t chunk = (F + 1023) / 1024;
+    const int64_t lo = (int64_t)threadIdx.x * chunk, hi = lo + chunk < F ? lo + chunk : F;
+    int64_t c = 0;
+    for (int64_t f = lo; f < hi; ++f)
+        c += ok[f] ? 0 : 1;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the 1024 chunk counts
+    for (int s = 1; s < 1024; s <<= 1) {
+        const int64_t v = (int)threadIdx.x >= s ? cnt[threadIdx.x - s] : 0;
+        __syncthreads();
+        cnt[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t pos = cnt[threadIdx.x] - c;
+    for (int64_t f = lo; f < hi; ++f)
+        if (!ok[f])
+            out[1 + pos++] = f;
+    if (threadIdx.x == 1023)
+        out[0] = cnt[1023];
+}
+
 inline int grid_for(int64_t work, int threads) { return (int)((work + threads - 1) / threads); }
 
 }  // namespace
@@ -183,12 +249,26 @@ int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipSt
     return check_launch(__func__);
 }
 
-int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale, float *llr,
-                    hipStream_t stream)
+int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
+                    const float *sigma_f, const float *scale_f, float *llr, hipStream_t stream)
 {
     const int64_t work = F * ((N + 3) / 4);
     hipLaunchKernelGGL(k_awgn_llr, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, F, N, cw, sigma, scale,
-                       llr);
+                       sigma_f, scale_f, llr);
+    return check_launch(__func__);
+}
+
+int launch_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
+                       int64_t N, int64_t K, int64_t *counters, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_frame_stats, dim3((unsigned)F), dim3(256), 0, stream, bits, info, iters, ok, N, K,
+                       (unsigned long long *)counters);
+    return check_launch(__func__);
+}
+
+int launch_compact_failed(const uint8_t *ok, int64_t F, int64_t *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_compact_failed, dim3(1), dim3(1024), 0, stream, ok, F, out);
     return check_launch(__func__);
 }
 

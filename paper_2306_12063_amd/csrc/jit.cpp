@@ -161,7 +161,8 @@ void jit_cache_clear()
 
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
-                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream)
+                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
+                      const int64_t *Fdev)
 {
     hipFunction_t fn;
     int rc = get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode), "ldpc_jit_decode", &fn);
@@ -169,7 +170,8 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
         return rc;
     long long Fll = (long long)F;
     void *args[] = {(void *)&llr, (void *)&fidx, (void *)&Fll, (void *)&max_iter, (void *)&alpha, (void *)&offset,
-                    (void *)&wq, (void *)&et, (void *)&wt, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
+                    (void *)&wq, (void *)&et, (void *)&wt, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok,
+                    (void *)&Fdev};
     return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "decode");
 }
 

@@ -384,8 +384,8 @@ int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *s
     return device_status(launch_random_bits(seed, F, K, info, (hipStream_t)stream), "ldpc_random_bits");
 }
 
-int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale, float *llr,
-                  void *stream)
+int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale,
+                  const float *sigma_f, const float *scale_f, float *llr, void *stream)
 {
     clear_error();
     if (F < 0 || N < 0)
@@ -396,7 +396,76 @@ int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float 
         return fail(LDPC_EINVAL, "null device pointer");
     if (N >= (int64_t(1) << 34))
         return fail(LDPC_ERANGE, "frame length too large for the noise counter");
-    return device_status(launch_awgn_llr(seed, F, N, cw, sigma, scale, llr, (hipStream_t)stream), "ldpc_awgn_llr");
+    if ((sigma_f == nullptr) != (scale_f == nullptr))
+        return fail(LDPC_EINVAL, "per-frame sigma and scale must be given together");
+    return device_status(launch_awgn_llr(seed, F, N, cw, sigma, scale, sigma_f, scale_f, llr, (hipStream_t)stream),
+                         "ldpc_awgn_llr");
+}
+
+int ldpc_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
+                     int64_t N, int64_t K, int64_t *counters, void *stream)
+{
+    clear_error();
+    if (F < 0 || K < 0 || N < K)
+        return fail(LDPC_EINVAL, "bad sizes F=%lld N=%lld K=%lld", (long long)F, (long long)N, (long long)K);
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({bits, info, counters}))
+        return fail(LDPC_EINVAL, "null device pointer (bits, info and counters are required)");
+    return device_status(launch_frame_stats(bits, info, iters, ok, F, N, K, counters, (hipStream_t)stream),
+                         "ldpc_frame_stats");
+}
+
+namespace {
+
+// Re-decodes, from their channel LLRs and with fresh state, the frames whose
+// ok flag is 0, with plain normalised (or offset) min-sum and early
+// termination; their bits, posteriors, iterations and ok are overwritten.
+int fallback(const int16_t *hbm, int Mb, int Nb, int Z, int path, const void *llr, int64_t F, int max_iter,
+             float alpha, int offset, int wq, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, int64_t *work,
+             hipStream_t stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters, ok, work}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits, iters, ok and work are required)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the fallback decoder needs run-time specialisation (LDPC_JIT=0 is set)");
+    DecodeLaunch lc = plan_decode(sc, path == 0 ? 4 : 2, 2);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    tuned_launch(sc, path, &lc);
+    if ((rc = launch_compact_failed(ok, F, work, stream)))
+        return device_status(rc, "fallback compaction");
+    const int mode = path == 0 ? 0 : (wq > 0 ? 1 : 0);
+    return launch_jit_decode(sc, lc, path, mode, llr, work + 1, F, max_iter, alpha, offset, wq, 1, nullptr, bits, post,
+                             iters, ok, stream, work);
+}
+
+}  // namespace
+
+int ldpc_fallback_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                      float alpha, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok, int64_t *work,
+                      void *stream)
+{
+    return fallback(hbm, Mb, Nb, Z, 0, llr, F, max_iter, alpha, 0, 0, bits, post, iters, ok, work,
+                    (hipStream_t)stream);
+}
+
+int ldpc_fallback_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter, int offset,
+                     int wq, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, int64_t *work, void *stream)
+{
+    if (offset < 0 || offset > 127 || wq < 0 || wq > 31)
+        return fail(LDPC_EINVAL, "offset must be in [0, 127] and wq in [0, 31]");
+    return fallback(hbm, Mb, Nb, Z, 1, llr, F, max_iter, 0.0f, offset, wq, bits, post, iters, ok, work,
+                    (hipStream_t)stream);
 }
 
 int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *stream)

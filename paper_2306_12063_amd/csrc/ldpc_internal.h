@@ -66,8 +66,11 @@ int launch_decode_i8(const Sched &sc, const DecodeLaunch &lc, const int8_t *llr,
 int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream);
 int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
 int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream);
-int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale, float *llr,
-                    hipStream_t stream);
+int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
+                    const float *sigma_f, const float *scale_f, float *llr, hipStream_t stream);
+int launch_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
+                       int64_t N, int64_t K, int64_t *counters, hipStream_t stream);
+int launch_compact_failed(const uint8_t *ok, int64_t F, int64_t *out, hipStream_t stream);
 
 // Run-time specialised decode kernels (jit.cpp). path: 0 FP32, 1 int8;
 // mode as in jit_decode.hip. LDPC_JIT=0 in the environment disables them.
@@ -75,7 +78,8 @@ bool jit_enabled();
 void jit_cache_clear();
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
-                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
+                      const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
+                      const int64_t *Fdev = nullptr);
 
 // Learned normalised min-sum training kernels (jit.cpp, jit_nms.hip).
 size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T);

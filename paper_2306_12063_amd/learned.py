@@ -1,0 +1,205 @@
+"""Training and evaluation of the learned normalised min-sum decoder.
+
+Every per-frame step runs in the library's kernels: Philox frame generation,
+direct encoding, BPSK/AWGN, the learned forward and its adjoint, decoding,
+fallback re-decoding and error counting. PyTorch provides device memory,
+the stream and the Adam optimiser; numpy draws the per-frame Eb/N0 values.
+
+    python -m paper_2306_12063_amd.learned --code wifi:5/6:81 --frames 262144
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+import synth
+from . import (ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_encode, ldpc_fallback_f32, ldpc_fallback_i8,
+               ldpc_frame_stats, ldpc_quantize_i8, ldpc_random_bits, ldpc_awgn_llr)
+from .nms import nms_loss, quantize_weights
+
+
+def make_frames(hbm, Z, F, ebn0_db, seed, device="cuda"):
+    """(info, codewords, channel LLRs) of F seeded frames; ebn0_db is a
+    number or an array of per-frame values (dB)."""
+    info = ldpc_code_info(hbm, Z)
+    N, K = info["N"], info["K"]
+    rate = K / N
+    bits = ldpc_random_bits(seed, F, K, device=device)
+    cw = ldpc_encode(hbm, Z, bits)
+    if np.isscalar(ebn0_db):
+        s2 = synth.sigma2_from_ebn0(float(ebn0_db), rate)
+        llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, math.sqrt(s2), 2.0 / s2)
+    else:
+        e = np.asarray(ebn0_db, dtype=np.float64)
+        s2 = 1.0 / (2.0 * rate * np.power(10.0, e / 10.0))
+        sigma = torch.from_numpy(np.sqrt(s2).astype(np.float32)).to(device)
+        scale = torch.from_numpy((2.0 / s2).astype(np.float32)).to(device)
+        llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, sigma, scale)
+    return bits, cw, llr
+
+
+def train(hbm, Z, T=10, frames=1 << 20, batch=4096, lr=1e-2, ebn0_range=(1.0, 4.0), seed=1, w0=0.75,
+          device="cuda", log_every=0):
+    """Trains w [T][Mb][Nb] with Adam on fresh frames (Eb/N0 uniform per frame)
+    through the kernels' forward and adjoint. Returns (w, loss history)."""
+    Mb, Nb = np.asarray(hbm).shape
+    w = torch.full((T, Mb, Nb), w0, dtype=torch.float32, device=device, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=lr)
+    rng = np.random.default_rng(seed)
+    history = []
+    steps = max(1, frames // batch)
+    for step in range(steps):
+        e = rng.uniform(ebn0_range[0], ebn0_range[1], batch)
+        _, cw, llr = make_frames(hbm, Z, batch, e, seed * 1000003 + step, device)
+        opt.zero_grad(set_to_none=True)
+        loss = nms_loss(w, llr, cw, hbm, Z).sum()
+        loss.backward()
+        opt.step()
+        history.append(float(loss.detach()))
+        if log_every and (step % log_every == 0 or step == steps - 1):
+            print(f"  step {step:4d}/{steps}  loss {history[-1]:.5f}", flush=True)
+    return w.detach(), history
+
+
+class _Dec:
+    """One decoder form of the comparison."""
+
+    def __init__(self, name, run, fallback):
+        self.name, self.run, self.fallback = name, run, fallback
+
+
+def decoders(hbm, Z, w, T=10):
+    """Plain NMS (alpha = 0.75), learned FP32 and learned int8 (1/16 steps);
+    each falls back to plain min-sum with 20 iterations for failed frames."""
+    wq = quantize_weights(w)
+
+    def plain(llr, q):
+        return ldpc_decode_f32(hbm, Z, llr, max_iter=T, alpha=0.75, early_term=True, want_post=False)
+
+    def learned(llr, q):
+        return ldpc_decode_f32(hbm, Z, llr, max_iter=T, w=w, early_term=True, want_post=False)
+
+    def learned8(llr, q):
+        return ldpc_decode_i8(hbm, Z, q, max_iter=T, wq_table=wq, early_term=True, want_post=False)
+
+    def fb32(llr, q, bits, iters, ok):
+        ldpc_fallback_f32(hbm, Z, llr, bits, iters, ok, max_iter=20, alpha=0.75)
+
+    def fb8(llr, q, bits, iters, ok):
+        ldpc_fallback_i8(hbm, Z, q, bits, iters, ok, max_iter=20, wq=12)
+
+    return [_Dec("plain_nms_f32", plain, fb32), _Dec("learned_f32", learned, fb32),
+            _Dec("learned_i8", learned8, fb8)]
+
+
+def sweep(hbm, Z, decs, ebn0_list, frames, chunk=1 << 17, seed=7, device="cuda", T=10):
+    """FER/BER/iterations per decoder and Eb/N0 point, first pass and after
+    fallback, and decode throughput (info bits per second of decode time)."""
+    info = ldpc_code_info(hbm, Z)
+    K = info["K"]
+    out = {d.name: [] for d in decs}
+    for pi, eb in enumerate(ebn0_list):
+        first = {d.name: torch.zeros(4, dtype=torch.int64, device=device) for d in decs}
+        final = {d.name: torch.zeros(4, dtype=torch.int64, device=device) for d in decs}
+        ms = {d.name: 0.0 for d in decs}
+        done = 0
+        ci = 0
+        while done < frames:
+            F = min(chunk, frames - done)
+            bits_in, _, llr = make_frames(hbm, Z, F, eb, seed * 7919 + pi * 104729 + ci, device)
+            q = ldpc_quantize_i8(llr)
+            for d in decs:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                bits, _, iters, ok = d.run(llr, q)
+                e1.record()
+                ldpc_frame_stats(bits, bits_in, iters, ok, counters=first[d.name])
+                d.fallback(llr, q, bits, iters, ok)
+                ldpc_frame_stats(bits, bits_in, iters, ok, counters=final[d.name])
+                torch.cuda.synchronize()
+                ms[d.name] += e0.elapsed_time(e1)
+            done += F
+            ci += 1
+        for d in decs:
+            a, b = first[d.name].cpu().numpy(), final[d.name].cpu().numpy()
+            out[d.name].append(dict(
+                ebn0=float(eb), frames=int(frames), fer=a[1] / frames, ber=a[0] / (frames * K),
+                mean_iters=a[2] / frames, failed_syndrome=int(a[3]),
+                # a frame that failed ran T first-pass iterations, then the fallback's
+                fer_fallback=b[1] / frames, mean_iters_total=(b[2] + T * a[3]) / frames,
+                gbit_s=frames * K / (ms[d.name] / 1e3) / 1e9))
+    return out
+
+
+def ebn0_at_fer(points, key="fer", target=1e-3):
+    """Eb/N0 where the FER crosses `target`, interpolated linearly in
+    log10(FER) between the bracketing sweep points (None if not crossed)."""
+    for a, b in zip(points, points[1:]):
+        fa, fb = a[key], b[key]
+        if fa >= target > fb:
+            if fb <= 0:
+                return b["ebn0"]
+            la, lb, lt = math.log10(fa), math.log10(fb), math.log10(target)
+            return a["ebn0"] + (b["ebn0"] - a["ebn0"]) * (la - lt) / (la - lb)
+    return None
+
+
+def iters_at(points, ebn0):
+    """Mean first-pass iterations at the sweep point nearest ebn0."""
+    p = min(points, key=lambda x: abs(x["ebn0"] - ebn0))
+    return p["mean_iters"]
+
+
+def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, seed=1, log_every=0):
+    """Trains a weight set for one code and compares the three decoder forms."""
+    if ebn0_list is None:
+        ebn0_list = [1.0 + 0.25 * k for k in range(21)]
+    t0 = time.perf_counter()
+    w, hist = train(hbm, Z, frames=train_frames, seed=seed, log_every=log_every)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = sweep(hbm, Z, decoders(hbm, Z, w), ebn0_list, eval_frames, seed=seed + 1)
+    summary = {}
+    e_plain = ebn0_at_fer(res["plain_nms_f32"])
+    for name, pts in res.items():
+        e = ebn0_at_fer(pts)
+        summary[name] = dict(ebn0_at_fer_1e3=e, gain_db=(None if e is None or e_plain is None else e_plain - e),
+                             mean_iters_at_plain_point=(iters_at(pts, e_plain) if e_plain is not None else None),
+                             gbit_s=float(np.mean([p["gbit_s"] for p in pts])))
+    if e_plain is not None:
+        base = summary["plain_nms_f32"]["mean_iters_at_plain_point"]
+        for name in summary:
+            it = summary[name]["mean_iters_at_plain_point"]
+            summary[name]["iter_reduction"] = (None if it is None or base == 0 else 1.0 - it / base)
+    return dict(train_seconds=t_train, loss_first=hist[0], loss_last=hist[-1], summary=summary, sweep=res)
+
+
+def _code(spec):
+    kind, rate, Z = spec.split(":")
+    Z = int(Z)
+    return (synth.wifi_code(rate, Z) if kind == "wifi" else synth.wimax_code(rate, Z)), Z
+
+
+def main():
+    ap = argparse.ArgumentParser(description="learned vs plain normalised min-sum on one GPU")
+    ap.add_argument("--code", default="wifi:5/6:81", help="wifi:<rate>:<Z> or wimax:<class>:<Z>")
+    ap.add_argument("--train-frames", type=int, default=1 << 20)
+    ap.add_argument("--eval-frames", type=int, default=1 << 18)
+    ap.add_argument("--ebn0", default="1:6:0.25", help="start:stop:step in dB")
+    ap.add_argument("--seed", type=int, default=1)
+    args = ap.parse_args()
+    a, b, s = (float(x) for x in args.ebn0.split(":"))
+    pts = list(np.round(np.arange(a, b + 1e-9, s), 4))
+    hbm, Z = _code(args.code)
+    r = compare(hbm, Z, args.train_frames, args.eval_frames, pts, args.seed, log_every=32)
+    r["code"] = args.code
+    print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,3 +92,11 @@ def test_encoder_structure_rejected_without_gpu():
     h = np.ascontiguousarray(h, np.int16)
     rc = P.lib().ldpc_encode(h.ctypes.data_as(C.c_void_p), 8, 24, 27, None, None, 4, None)
     assert rc == P.LDPC_ESTRUCT
+
+
+def test_ebn0_at_fer_interpolation():
+    from paper_2306_12063_amd.learned import ebn0_at_fer
+    pts = [dict(ebn0=1.0, fer=1e-1), dict(ebn0=2.0, fer=1e-2), dict(ebn0=3.0, fer=1e-4)]
+    assert ebn0_at_fer(pts) == pytest.approx(2.5)
+    assert ebn0_at_fer(pts, target=1e-2) == pytest.approx(2.0)
+    assert ebn0_at_fer(pts[:2]) is None
