@@ -207,6 +207,41 @@ int ldpc_fallback_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *ll
                      int wq, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, int64_t *work, void *stream);
 
 /*
+ * Code sets and batched decoding of frames of different codes in one
+ * persistent launch (different Z, rate and length).
+ *
+ * ldpc_codeset_create: compiles `ncodes` base matrices (host pointers
+ *   hbm[c], each int16 [Mb[c]][Nb[c]], expansion Z[c]) into device tables on
+ *   the current device. Codes with the same block structure share a kernel
+ *   body. *out receives an opaque handle owned by the caller (free it with
+ *   ldpc_codeset_destroy). At most 1024 codes; each code needs Z <= 256.
+ * ldpc_codeset_info: out[8] = {N, K, M, E, dmax, structure class, frames per
+ *   work item, number of classes} of code `code`.
+ * ldpc_batch_work_bytes: size of the device scratch buffer for F frames.
+ * ldpc_decode_batch_f32 / _i8: decodes F frames; frame f belongs to code
+ *   code_id[f] (device i32 [F]) and its N values start at element off[f]
+ *   (device i64 [F]) of llr, and at the same offset in bits and post; iters
+ *   and ok are [F]. Frames are grouped by code on the device and cut into work
+ *   items that the workgroups of a persistent grid take from an atomic queue.
+ *   Arithmetic and arguments as ldpc_decode_f32 (alpha) / ldpc_decode_i8
+ *   (offset, wq; no weight table). Frames whose code id is outside
+ *   [0, ncodes) are not decoded. No host synchronisation: the call can be
+ *   captured in a hipGraph. Calls that share a work buffer must not overlap.
+ */
+typedef struct ldpc_codeset ldpc_codeset;
+int ldpc_codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, const int *Z, int ncodes,
+                        ldpc_codeset **out);
+void ldpc_codeset_destroy(ldpc_codeset *cs);
+int ldpc_codeset_info(const ldpc_codeset *cs, int code, int64_t out[8]);
+size_t ldpc_batch_work_bytes(const ldpc_codeset *cs, int64_t F);
+int ldpc_decode_batch_f32(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const float *llr,
+                          int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits, float *post,
+                          int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
+int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const int8_t *llr,
+                         int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits, int16_t *post,
+                         int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
+
+/*
  * int8 quantiser for channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rounding half to even. llr: device f32 [n], q: device i8 [n].
  */

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
-    "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -44,6 +44,13 @@ EXPORTS = {
     "ldpc_nms_ckpt_bytes": ([_p, _i32, _i32, _i32, _i64, _i32], C.c_size_t),
     "ldpc_nms_fwd": ([_p, _i32, _i32, _i32, _p, _p, _i64, _i32, _p, _p, C.c_size_t, _p, _p, _p], _i32),
     "ldpc_nms_bwd": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _p, _p, C.c_size_t, _p, _p, _p], _i32),
+    "ldpc_codeset_create": ([_p, _p, _p, _p, _i32, _p], _i32),
+    "ldpc_codeset_destroy": ([_p], None),
+    "ldpc_codeset_info": ([_p, _i32, _p], _i32),
+    "ldpc_batch_work_bytes": ([_p, _i64], C.c_size_t),
+    "ldpc_decode_batch_f32": ([_p, _p, _p, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p], _i32),
+    "ldpc_decode_batch_i8": ([_p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p],
+                             _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -332,3 +339,68 @@ def ldpc_nms_bwd(hbm, Z, cw, w, ckpt, dloss, grad_w=None, stream=None):
                               _dev(dloss, torch.float32, "dloss", (T,)),
                               _dev(grad_w, torch.float32, "grad_w", (T, Mb, Nb)), _stream(stream)), "ldpc_nms_bwd")
     return grad_w
+
+
+class Codeset:
+    """Several codes decoded together by the batched persistent kernel
+    (ldpc_codeset_create / ldpc_decode_batch_*). codes: list of (hbm, Z)."""
+
+    def __init__(self, codes):
+        self._h = [_hbm(h) for h, _ in codes]
+        n = len(self._h)
+        ptrs = (C.c_void_p * n)(*[h.ctypes.data for h in self._h])
+        Mb = (C.c_int * n)(*[h.shape[0] for h in self._h])
+        Nb = (C.c_int * n)(*[h.shape[1] for h in self._h])
+        Zs = (C.c_int * n)(*[int(z) for _, z in codes])
+        handle = C.c_void_p()
+        _check(lib().ldpc_codeset_create(ptrs, Mb, Nb, Zs, n, C.byref(handle)), "ldpc_codeset_create")
+        self._cs = handle
+        self.n = n
+        self.info = []
+        out = np.zeros(8, np.int64)
+        for c in range(n):
+            _check(lib().ldpc_codeset_info(self._cs, c, out.ctypes.data_as(C.c_void_p)), "ldpc_codeset_info")
+            self.info.append(dict(N=int(out[0]), K=int(out[1]), M=int(out[2]), E=int(out[3]), dmax=int(out[4]),
+                                  cls=int(out[5]), G=int(out[6]), nclass=int(out[7])))
+
+    def __del__(self):
+        cs, self._cs = getattr(self, "_cs", None), None
+        if cs and _lib is not None:
+            _lib.ldpc_codeset_destroy(cs)
+
+    def work_bytes(self, F):
+        return int(lib().ldpc_batch_work_bytes(self._cs, int(F)))
+
+    def _decode(self, name, code_id, off, llr, total, F, args_mid, bits, post, iters, ok, work, stream, llr_dtype,
+                post_dtype, want_post):
+        torch = _torch()
+        dev = llr.device
+        if work is None:
+            work = torch.empty(self.work_bytes(F), dtype=torch.uint8, device=dev)
+        bits = torch.empty(total, dtype=torch.uint8, device=dev) if bits is None else bits
+        if post is None and want_post:
+            post = torch.empty(total, dtype=post_dtype, device=dev)
+        iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+        ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+        fn = getattr(lib(), name)
+        _check(fn(self._cs, _dev(code_id, torch.int32, "code_id", (F,)), _dev(off, torch.int64, "off", (F,)),
+                  _dev(llr, llr_dtype, "llr"), F, *args_mid, _dev(bits, torch.uint8, "bits", (total,)),
+                  _opt(post, post_dtype, "post", (total,)), _dev(iters, torch.int32, "iters", (F,)),
+                  _opt(ok, torch.uint8, "ok", (F,)), _dev(work, torch.uint8, "work"), work.numel(),
+                  _stream(stream)), name)
+        return bits, post, iters, ok
+
+    def decode_f32(self, code_id, off, llr, max_iter=10, alpha=0.75, early_term=True, bits=None, post=None,
+                   iters=None, ok=None, work=None, want_post=True, stream=None):
+        """Ragged batch: frame f of code code_id[f] occupies llr[off[f] : off[f] + N]."""
+        torch = _torch()
+        return self._decode("ldpc_decode_batch_f32", code_id, off, llr, llr.numel(), code_id.numel(),
+                            (int(max_iter), float(alpha), int(bool(early_term))), bits, post, iters, ok, work, stream,
+                            torch.float32, torch.float32, want_post)
+
+    def decode_i8(self, code_id, off, llr, max_iter=10, offset=1, wq=0, early_term=True, bits=None, post=None,
+                  iters=None, ok=None, work=None, want_post=True, stream=None):
+        torch = _torch()
+        return self._decode("ldpc_decode_batch_i8", code_id, off, llr, llr.numel(), code_id.numel(),
+                            (int(max_iter), int(offset), int(wq), int(bool(early_term))), bits, post, iters, ok,
+                            work, stream, torch.int8, torch.int16, want_post)

@@ -23,7 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 GPU = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-JIT_SOURCES = [("jit_decode.hip", "kJitDecodeSource"), ("jit_nms.hip", "kJitNmsSource")]
+JIT_SOURCES = [("jit_decode.hip", "kJitDecodeSource"), ("jit_nms.hip", "kJitNmsSource"),
+               ("jit_batch.hip", "kJitBatchSource")]
 
 
 def _embed_jit_source():
@@ -47,6 +48,7 @@ def _units():
     units = [("ldpc_capi.cpp", [], "ldpc_capi.o"),
              ("jit.cpp", [], "jit.o"),
              ("tune.cpp", [], "tune.o"),
+             ("batch.cpp", [], "batch.o"),
              (os.path.join(OBJ, "jit_source.cpp"), [], "jit_source.o"),
              ("decode_dispatch.cpp", [], "decode_dispatch.o"),
              ("frame_kernels.hip", [], "frame_kernels.o")]

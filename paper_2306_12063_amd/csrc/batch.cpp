@@ -1,0 +1,320 @@
+// Code sets and the batched (mixed-code) decode path.
+//
+// A code set holds several codes. Codes with the same block structure
+// (block rows, block columns and non-zero block positions) form a class:
+// the persistent kernel of jit_batch.hip is compiled once per code set with
+// each class's degrees and columns as constants, and reads each code's Z,
+// shifts and layout from the device tables built here. A batched decode is
+// five stream-ordered kernels (clear, histogram by code, plan of work items,
+// scatter of frame indices, persistent decode) with no host synchronisation,
+// so a caller may capture it in a hipGraph.
+#include <string.h>
+
+#include <algorithm>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ldpc_internal.h"
+
+struct ldpc_codeset {
+    int device = 0;
+    int ncodes = 0;
+    std::vector<ldpc::Sched> sc;
+    std::vector<int> cls;              // class of each code
+    std::vector<int> class_rep;        // a code of each class
+    int cmb = 0, cd = 0;               // largest block-row count and degree
+    // per arithmetic path (0 FP32, 1 int16 posteriors): device tables
+    void *d_codes[2] = {nullptr, nullptr};
+    void *d_etab[2] = {nullptr, nullptr};
+    size_t lds_elems[2] = {0, 0};
+    std::vector<int> G;                // frames per work item of each code
+};
+
+namespace ldpc {
+
+namespace {
+
+struct CodeRec {
+    int Z, N, cls, G, FWp, etab, pad0, pad1;
+};
+
+bool same_structure(const Sched &a, const Sched &b)
+{
+    if (a.Mb != b.Mb || a.Nb != b.Nb)
+        return false;
+    for (int i = 0; i < a.Mb; ++i) {
+        if (a.deg[i] != b.deg[i])
+            return false;
+        for (int e = 0; e < a.deg[i]; ++e)
+            if ((a.edge[i][e] >> 16) != (b.edge[i][e] >> 16))
+                return false;
+    }
+    return true;
+}
+
+int fwp_for(int G, int path)
+{
+    int FWp = G;
+    if (path == 0)
+        return FWp | 1;
+    while (FWp % 4 != 2)
+        ++FWp;
+    return FWp;
+}
+
+std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
+{
+    std::ostringstream o;
+    const int nclass = (int)cs.class_rep.size();
+    o << "#define LDPC_THREADS " << kMaxThreads << "\n#define LDPC_LDS " << cs.lds_elems[path]
+      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n#define LDPC_NCLASS " << nclass
+      << "\n#define LDPC_CMB " << cs.cmb << "\n#define LDPC_CD " << cs.cd << "\n";
+    o << "__device__ constexpr int kMBc[" << nclass << "] = {";
+    for (int c = 0; c < nclass; ++c)
+        o << cs.sc[cs.class_rep[c]].Mb << (c + 1 < nclass ? "," : "};\n");
+    o << "__device__ constexpr int kDegc[" << nclass << "][" << cs.cmb << "] = {";
+    for (int c = 0; c < nclass; ++c) {
+        const Sched &s = cs.sc[cs.class_rep[c]];
+        o << "{";
+        for (int i = 0; i < cs.cmb; ++i)
+            o << (i < s.Mb ? s.deg[i] : 0) << (i + 1 < cs.cmb ? "," : "");
+        o << "}" << (c + 1 < nclass ? "," : "};\n");
+    }
+    o << "#define LDPC_CLASS_CASES";
+    for (int c = 0; c < nclass; ++c)
+        o << " LDPC_CLASS_CASE(" << c << ")";
+    o << "\n";
+    return o.str();
+}
+
+}  // namespace
+
+extern const char kJitBatchSource[];
+
+int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, const int *Z, int n, ldpc_codeset **out)
+{
+    if (!hbm || !Mb || !Nb || !Z || !out || n < 1)
+        return fail(LDPC_EINVAL, "null argument or empty code set");
+    if (n > 1024)
+        return fail(LDPC_ERANGE, "a code set holds at most 1024 codes");
+    ldpc_codeset *cs = new ldpc_codeset();
+    cs->ncodes = n;
+    cs->sc.resize(n);
+    for (int c = 0; c < n; ++c) {
+        int rc = compile_sched(hbm[c], Mb[c], Nb[c], Z[c], true, &cs->sc[c]);
+        if (rc) {
+            delete cs;
+            return rc;
+        }
+        int k = 0;
+        for (; k < (int)cs->class_rep.size(); ++k)
+            if (same_structure(cs->sc[cs->class_rep[k]], cs->sc[c]))
+                break;
+        if (k == (int)cs->class_rep.size())
+            cs->class_rep.push_back(c);
+        cs->cls.push_back(k);
+        cs->cmb = std::max(cs->cmb, cs->sc[c].Mb);
+        cs->cd = std::max(cs->cd, cs->sc[c].dmax);
+        const int G = std::min(64, kMaxThreads / cs->sc[c].Z);
+        if (G < 1) {
+            delete cs;
+            return fail(LDPC_ERANGE, "code %d: Z=%d exceeds the batched kernel's workgroup", c, Z[c]);
+        }
+        cs->G.push_back(G);
+    }
+    if (hipGetDevice(&cs->device) != hipSuccess) {
+        delete cs;
+        return fail(LDPC_EDEVICE, "hipGetDevice failed");
+    }
+    for (int path = 0; path < 2; ++path) {
+        std::vector<CodeRec> rec(n);
+        std::vector<int> etab;
+        size_t lds = 0;
+        for (int c = 0; c < n; ++c) {
+            const Sched &s = cs->sc[c];
+            const int G = cs->G[c], FWp = fwp_for(G, path);
+            const size_t bytes = (size_t)s.N * FWp * (path == 0 ? 4 : 2);
+            if (bytes > (size_t)kLdsBudget) {
+                ldpc_codeset_destroy(cs);
+                return fail(LDPC_ERANGE, "code %d (N=%d) does not fit the batched kernel's LDS budget", c, s.N);
+            }
+            lds = std::max(lds, (size_t)s.N * FWp);
+            rec[c] = CodeRec{s.Z, s.N, cs->cls[c], G, FWp, (int)(etab.size() / 2), 0, 0};
+            for (int i = 0; i < cs->cmb; ++i)
+                for (int e = 0; e < cs->cd; ++e) {
+                    int base = 0, thr = 1 << 30;
+                    if (i < s.Mb && e < s.deg[i]) {
+                        const int col = (int)(s.edge[i][e] >> 16), sh = (int)(s.edge[i][e] & 0xffffu);
+                        base = (col * s.Z + sh) * FWp;
+                        thr = s.Z - sh;
+                    }
+                    etab.push_back(base);
+                    etab.push_back(thr);
+                }
+        }
+        cs->lds_elems[path] = lds;
+        if (hipMalloc(&cs->d_codes[path], rec.size() * sizeof(CodeRec)) != hipSuccess ||
+            hipMalloc(&cs->d_etab[path], etab.size() * sizeof(int)) != hipSuccess) {
+            ldpc_codeset_destroy(cs);
+            return fail(LDPC_ENOMEM, "code set: device allocation failed");
+        }
+        if (hipMemcpy(cs->d_codes[path], rec.data(), rec.size() * sizeof(CodeRec), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(cs->d_etab[path], etab.data(), etab.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            ldpc_codeset_destroy(cs);
+            return fail(LDPC_EDEVICE, "code set: copy to device failed");
+        }
+    }
+    *out = cs;
+    return LDPC_OK;
+}
+
+// Work buffer: head (items, queue, hist[ncodes], cursor[ncodes]), perm[F]
+// (padded to an even count so the items stay 16-byte aligned), items[F + ncodes].
+size_t batch_work_bytes(const ldpc_codeset *cs, int64_t F)
+{
+    return (size_t)(2 + 2 * cs->ncodes + F + (F & 1)) * sizeof(int64_t) + (size_t)(F + cs->ncodes) * 4 * sizeof(int);
+}
+
+int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_t *code_id, const int64_t *off,
+                        const void *llr, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
+                        uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, void *work, hipStream_t stream)
+{
+    const std::string pre = batch_prelude(*cs, path, mode);
+    hipFunction_t f_clear, f_hist, f_plan, f_scatter, f_dec;
+    int rc;
+    if ((rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_clear", &f_clear)) ||
+        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_hist", &f_hist)) ||
+        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_plan", &f_plan)) ||
+        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_scatter", &f_scatter)) ||
+        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_decode", &f_dec)))
+        return rc;
+    int64_t *head = (int64_t *)work;
+    int64_t *perm = head + 2 + 2 * cs->ncodes;
+    int *items = (int *)(perm + F + (F & 1));
+    int nc = cs->ncodes;
+    long long Fll = (long long)F;
+    const void *codes = cs->d_codes[path], *etab = cs->d_etab[path];
+    void *a_clear[] = {(void *)&head, (void *)&nc};
+    void *a_hist[] = {(void *)&code_id, (void *)&Fll, (void *)&nc, (void *)&head};
+    void *a_plan[] = {(void *)&codes, (void *)&nc, (void *)&head, (void *)&items};
+    void *a_scatter[] = {(void *)&code_id, (void *)&Fll, (void *)&nc, (void *)&head, (void *)&perm};
+    const unsigned fblocks = (unsigned)((F + 255) / 256);
+    if ((rc = jit_launch(f_clear, (unsigned)((2 + 2 * nc + 255) / 256), 256, stream, a_clear, "batch clear")) ||
+        (rc = jit_launch(f_hist, fblocks, 256, stream, a_hist, "batch histogram")) ||
+        (rc = jit_launch(f_plan, 1, 1024, stream, a_plan, "batch plan")) ||
+        (rc = jit_launch(f_scatter, fblocks, 256, stream, a_scatter, "batch scatter")))
+        return rc;
+    // persistent grid: as many workgroups as can be resident at once
+    int per_cu = 0, cus = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f_dec, kMaxThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cs->device) != hipSuccess)
+        return fail(LDPC_EDEVICE, "occupancy query failed");
+    const unsigned grid = (unsigned)std::max(1, per_cu * cus);
+    int64_t *nitems = head;
+    unsigned long long *queue = (unsigned long long *)(head + 1);
+    void *a_dec[] = {(void *)&items, (void *)&nitems, (void *)&queue, (void *)&perm, (void *)&off, (void *)&codes,
+                     (void *)&etab, (void *)&llr, (void *)&max_iter, (void *)&alpha, (void *)&offset, (void *)&wq,
+                     (void *)&et, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
+    return jit_launch(f_dec, grid, kMaxThreads, stream, a_dec, "batch decode");
+}
+
+}  // namespace ldpc
+
+using namespace ldpc;
+
+extern "C" {
+
+int ldpc_codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, const int *Z, int ncodes,
+                        ldpc_codeset **out)
+{
+    clear_error();
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "code sets need run-time specialisation (LDPC_JIT=0 is set)");
+    return codeset_create(hbm, Mb, Nb, Z, ncodes, out);
+}
+
+void ldpc_codeset_destroy(ldpc_codeset *cs)
+{
+    if (!cs)
+        return;
+    for (int p = 0; p < 2; ++p) {
+        if (cs->d_codes[p])
+            (void)hipFree(cs->d_codes[p]);
+        if (cs->d_etab[p])
+            (void)hipFree(cs->d_etab[p]);
+    }
+    delete cs;
+}
+
+int ldpc_codeset_info(const ldpc_codeset *cs, int code, int64_t out[8])
+{
+    clear_error();
+    if (!cs || !out || code < 0 || code >= cs->ncodes)
+        return fail(LDPC_EINVAL, "bad code set, code index or output pointer");
+    const Sched &s = cs->sc[code];
+    out[0] = s.N;
+    out[1] = s.K;
+    out[2] = s.M;
+    out[3] = s.E;
+    out[4] = s.dmax;
+    out[5] = cs->cls[code];
+    out[6] = cs->G[code];
+    out[7] = (int64_t)cs->class_rep.size();
+    return LDPC_OK;
+}
+
+size_t ldpc_batch_work_bytes(const ldpc_codeset *cs, int64_t F)
+{
+    if (!cs || F < 0)
+        return 0;
+    return batch_work_bytes(cs, F);
+}
+
+static int batch_common(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const void *llr,
+                        int64_t F, int max_iter, const void *bits, const int32_t *iters, void *work, size_t work_bytes)
+{
+    clear_error();
+    if (!cs)
+        return fail(LDPC_EINVAL, "null code set");
+    if (F < 0 || max_iter < 1)
+        return fail(LDPC_EINVAL, "F must be >= 0 and max_iter >= 1");
+    if (F > ((int64_t)1 << 31) - 1)
+        return fail(LDPC_ERANGE, "batch larger than 2^31 - 1 frames");
+    if (F > 0 && (!code_id || !off || !llr || !bits || !iters || !work))
+        return fail(LDPC_EINVAL, "null device pointer (code_id, off, llr, bits, iters and work are required)");
+    if (F > 0 && work_bytes < batch_work_bytes(cs, F))
+        return fail(LDPC_EINVAL, "work buffer too small: %zu < %zu bytes", work_bytes, batch_work_bytes(cs, F));
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != cs->device)
+        return fail(LDPC_EINVAL, "the code set belongs to device %d", cs->device);
+    return LDPC_OK;
+}
+
+int ldpc_decode_batch_f32(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const float *llr,
+                          int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits, float *post,
+                          int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
+{
+    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    if (rc || F == 0)
+        return rc;
+    return launch_batch_decode(cs, 0, 0, code_id, off, llr, F, max_iter, alpha, 0, 0, early_term, bits, post, iters,
+                               ok, work, (hipStream_t)stream);
+}
+
+int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const int8_t *llr,
+                         int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits, int16_t *post,
+                         int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
+{
+    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    if (rc || F == 0)
+        return rc;
+    if (offset < 0 || offset > 127 || wq < 0 || wq > 31)
+        return fail(LDPC_EINVAL, "offset must be in [0, 127] and wq in [0, 31]");
+    return launch_batch_decode(cs, 1, wq > 0 ? 1 : 0, code_id, off, llr, F, max_iter, 0.0f, offset, wq, early_term,
+                               bits, post, iters, ok, work, (hipStream_t)stream);
+}
+
+}  // extern "C"

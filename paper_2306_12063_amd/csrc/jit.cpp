@@ -22,6 +22,7 @@ namespace ldpc {
 // Kernel sources, embedded at build time from jit_decode.hip and jit_nms.hip.
 extern const char kJitDecodeSource[];
 extern const char kJitNmsSource[];
+extern const char kJitBatchSource[];
 
 namespace {
 
@@ -144,6 +145,16 @@ int launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stre
 }
 
 }  // namespace
+
+int jit_function(const char *tag, const char *src, const std::string &pre, const char *name, hipFunction_t *fn)
+{
+    return get_function(tag, src, pre, name, fn);
+}
+
+int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what)
+{
+    return launch(fn, blocks, threads, stream, args, what);
+}
 
 bool jit_enabled()
 {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/ldpc.h"
 
 namespace ldpc {
@@ -76,6 +78,9 @@ int launch_compact_failed(const uint8_t *ok, int64_t F, int64_t *out, hipStream_
 // mode as in jit_decode.hip. LDPC_JIT=0 in the environment disables them.
 bool jit_enabled();
 void jit_cache_clear();
+// Function `name` of the module built from prelude + source (cached per device).
+int jit_function(const char *tag, const char *src, const std::string &pre, const char *name, hipFunction_t *fn);
+int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what);
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,

@@ -1,0 +1,144 @@
+"""GPU parity of the batched persistent decoder on a ragged mix of codes
+(WiMAX-shaped, 6 rate classes x 19 expansion factors): every frame must
+decode exactly as the oracle decodes it with its own code; the decode must
+also replay exactly from a captured graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2306_12063_amd as P
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def wimax_set():
+    codes = synth.wimax_code_set()
+    return codes, P.Codeset([(h, Z) for _, Z, h in codes])
+
+
+def _ragged(codes, F, ebn0, seed, frames_per_code=None):
+    rng = np.random.default_rng(seed)
+    cid = rng.integers(0, len(codes), F).astype(np.int32)
+    Ns = np.array([h.shape[1] * Z for _, Z, h in codes])
+    off = np.zeros(F, np.int64)
+    off[1:] = np.cumsum(Ns[cid])[:-1]
+    total = int(Ns[cid].sum())
+    llr = np.zeros(total, np.float32)
+    per = {}
+    for c in np.unique(cid):
+        idx = np.flatnonzero(cid == c)
+        _, Z, h = codes[c]
+        _, _, l = oracle.llr_frames(h, Z, len(idx), ebn0, seed + 31 * int(c))
+        N = Ns[c]
+        for k, f in enumerate(idx):
+            llr[off[f]:off[f] + N] = l[k]
+        per[int(c)] = (idx, l)
+    return cid, off, llr, total, per
+
+
+def test_codeset_classes(wimax_set):
+    codes, cs = wimax_set
+    assert cs.n == 114
+    assert cs.info[0]["nclass"] == 6
+    for c, (cls, Z, h) in enumerate(codes):
+        assert cs.info[c]["N"] == 24 * Z and cs.info[c]["G"] == min(64, 256 // Z)
+
+
+@pytest.mark.parametrize("path", ["f32", "i8"])
+@pytest.mark.parametrize("et", [True, False])
+def test_batch_matches_oracle(wimax_set, path, et):
+    codes, cs = wimax_set
+    F = 400
+    cid, off, llr, total, per = _ragged(codes, F, 2.0, 5)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    if path == "f32":
+        bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=8, alpha=0.75, early_term=et)
+    else:
+        q = oracle.quantize_i8(llr)
+        bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(q), max_iter=8, offset=1, early_term=et)
+    torch.cuda.synchronize()
+    bits, post, iters, ok = (t.cpu().numpy() for t in (bits, post, iters, ok))
+    for c, (idx, l) in per.items():
+        _, Z, h = codes[c]
+        N = 24 * Z
+        if path == "f32":
+            wb, wp, wi, wo = oracle.decode_f32(h, Z, l, max_iter=8, alpha=0.75, early_term=et)
+        else:
+            wb, wp, wi, wo = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=8, offset=1, early_term=et)
+        for k, f in enumerate(idx):
+            assert np.array_equal(bits[off[f]:off[f] + N], wb[k]), (c, f)
+            assert np.array_equal(post[off[f]:off[f] + N], wp[k]), (c, f)
+        assert np.array_equal(iters[idx], wi) and np.array_equal(ok[idx], wo), c
+
+
+def test_batch_graph_replay(wimax_set):
+    codes, cs = wimax_set
+    F = 300
+    cid, off, llr, total, per = _ragged(codes, F, 1.5, 9)
+    d_cid, d_off, d_llr = (torch.from_numpy(x).to(DEV) for x in (cid, off, llr))
+    work = torch.empty(cs.work_bytes(F), dtype=torch.uint8, device=DEV)
+    out = [torch.empty(total, dtype=torch.uint8, device=DEV), torch.empty(total, dtype=torch.float32, device=DEV),
+           torch.empty(F, dtype=torch.int32, device=DEV), torch.empty(F, dtype=torch.uint8, device=DEV)]
+    eager = [t.clone() for t in cs.decode_f32(d_cid, d_off, d_llr, max_iter=10, work=work)]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):       # warm up on the capture stream
+        cs.decode_f32(d_cid, d_off, d_llr, max_iter=10, bits=out[0], post=out[1], iters=out[2], ok=out[3], work=work)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cs.decode_f32(d_cid, d_off, d_llr, max_iter=10, bits=out[0], post=out[1], iters=out[2], ok=out[3], work=work)
+    for rep in range(3):
+        for t in out:
+            t.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, eager):
+            assert torch.equal(a, b), rep
+        # unrelated eager work between replays
+        cs.decode_i8(d_cid, d_off, torch.zeros(total, dtype=torch.int8, device=DEV), max_iter=2)
+        torch.cuda.synchronize()
+
+
+def test_batch_full_size_sampled(wimax_set):
+    # 2^18 frames with uniformly drawn code ids in one persistent launch;
+    # the oracle checks a sample of frames.
+    codes, cs = wimax_set
+    F = 1 << 18
+    rng = np.random.default_rng(3)
+    cid = rng.integers(0, len(codes), F).astype(np.int32)
+    Ns = np.array([h.shape[1] * Z for _, Z, h in codes])
+    off = np.zeros(F, np.int64)
+    off[1:] = np.cumsum(Ns[cid])[:-1]
+    total = int(Ns[cid].sum())
+    llr = torch.empty(total, dtype=torch.float32, device=DEV)
+    d_off = torch.from_numpy(off).to(DEV)
+    for c in range(len(codes)):
+        idx = np.flatnonzero(cid == c)
+        if len(idx) == 0:
+            continue
+        _, Z, h = codes[c]
+        N, K = 24 * Z, (24 - h.shape[0]) * Z
+        s2 = synth.sigma2_from_ebn0(2.0, K / N)
+        cw = P.ldpc_encode(h, Z, P.ldpc_random_bits(100 + c, len(idx), K))
+        l = P.ldpc_awgn_llr(200 + c, cw, float(np.sqrt(s2)), 2.0 / s2)
+        pos = (d_off[torch.from_numpy(idx).to(DEV)][:, None] + torch.arange(N, device=DEV)[None, :]).reshape(-1)
+        llr[pos] = l.reshape(-1)
+    bits, post, iters, ok = cs.decode_f32(torch.from_numpy(cid).to(DEV), d_off, llr, max_iter=10, early_term=False)
+    torch.cuda.synchronize()
+    sample = rng.choice(F, 40, replace=False)
+    lh = llr.cpu().numpy()
+    bh, ph, ih = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+    for f in sample:
+        _, Z, h = codes[cid[f]]
+        N = 24 * Z
+        wb, wp, wi, _ = oracle.decode_f32(h, Z, lh[off[f]:off[f] + N][None], max_iter=10, early_term=False)
+        assert np.array_equal(bh[off[f]:off[f] + N], wb[0]) and np.array_equal(ph[off[f]:off[f] + N], wp[0])
+        assert ih[f] == wi[0]
