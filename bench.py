@@ -186,7 +186,7 @@ def main():
                         valu_tops=ops / (ms / 1e3) / 1e12, hbm_gbs=hbm_b / (ms / 1e3) / 1e9,
                         alg_ops=ops, hbm_bytes=hbm_b))
     dom = max(per, key=lambda p: p["ms"])
-    sha = source_sha("decode_f32.hip" if dom["kernel"] == "decode_f32" else "decode_i8.hip", "decode_common.h")
+    sha = source_sha("jit_decode.hip")
     roofline = {"bound": "alu", "achieved": round(dom["valu_tops"], 3), "peak": round(PEAK_VALU_TOPS, 1),
                 "unit": "TOP/s", "frac": round(dom["valu_tops"] / PEAK_VALU_TOPS, 4),
                 "traffic": measured_traffic(dom["kernel"], sha),

@@ -119,11 +119,12 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
 /*
  * Decode-layout autotuner. Times the code-specialised decode kernel of
  * `path` (0 FP32, 1 int8) over candidate layouts -- frame groups per
- * workgroup, frames per thread, and whether gather addresses stay in
- * registers across iterations -- on F zero-valued frames at max_iter fixed
+ * workgroup, frames per thread, and how many block rows keep their gather
+ * addresses in registers across iterations -- on F zero-valued frames at max_iter fixed
  * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
  * this code in this process (until ldpc_cache_clear). out[5] receives
- * {G, KF, FWp, threads, hoist} of the winner and *ms its time per launch.
+ * {G, KF, FWp, threads, hoisted block rows} of the winner and *ms its time
+ * per launch.
  * Synchronises `stream`; allocates and frees temporary device buffers.
  * LDPC_ERANGE if run-time specialisation is disabled (LDPC_JIT=0).
  */

@@ -170,6 +170,28 @@ void jit_cache_clear()
     g_cache.clear();
 }
 
+DecodeLaunch jit_default_launch(const Sched &sc, int path)
+{
+    DecodeLaunch lc = plan_decode(sc, 4, 1);   // FP32 posteriors in LDS on both paths
+    (void)path;
+    const int per_row = sc.E / sc.Z;          // messages (and gather addresses) per thread
+    lc.hoist = 2 * per_row <= 176 ? sc.Mb : 0;
+    return lc;
+}
+
+int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes)
+{
+    hipFunction_t fn;
+    int rc = get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode), "ldpc_jit_decode", &fn);
+    if (rc)
+        return rc;
+    int v = 0;
+    if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipFuncGetAttribute failed");
+    *bytes = (size_t)v;
+    return LDPC_OK;
+}
+
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,

@@ -113,10 +113,10 @@ DecodeLaunch make_launch(const Sched &sc, int elem_bytes, int G, int KF, int max
     else
         while (FWp % 4 != 2)
             ++FWp;                          // odd dword stride for 2-byte elements
-    const size_t lds = (size_t)sc.N * FWp * elem_bytes;
+    const size_t lds = (size_t)(sc.N + sc.Z) * FWp * elem_bytes;   // one column block of padding
     if (lds > (size_t)kLdsBudget)
         return lc;
-    lc = DecodeLaunch{G, KF, FW, FWp, ((G * sc.Z + 63) / 64) * 64, lds, 1};
+    lc = DecodeLaunch{G, KF, FW, FWp, ((G * sc.Z + 63) / 64) * 64, lds, 0};
     return lc;
 }
 
@@ -256,6 +256,7 @@ int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr,
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     if (jit_enabled()) {
+        lc = jit_default_launch(sc, 0);
         tuned_launch(sc, 0, &lc);
         return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits,
                                  post, iters, ok, (hipStream_t)stream);
@@ -288,6 +289,7 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     if (jit_enabled()) {
+        lc = jit_default_launch(sc, 1);
         tuned_launch(sc, 1, &lc);
         return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset,
                                  wq, early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream);
@@ -438,7 +440,7 @@ int fallback(const int16_t *hbm, int Mb, int Nb, int Z, int path, const void *ll
         return fail(LDPC_EINVAL, "null device pointer (llr, bits, iters, ok and work are required)");
     if (!jit_enabled())
         return fail(LDPC_ERANGE, "the fallback decoder needs run-time specialisation (LDPC_JIT=0 is set)");
-    DecodeLaunch lc = plan_decode(sc, path == 0 ? 4 : 2, 2);
+    DecodeLaunch lc = jit_default_launch(sc, path);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     tuned_launch(sc, path, &lc);

@@ -55,7 +55,7 @@ struct DecodeLaunch {
     int FWp;     // LDS row stride in elements (FW, padded against bank conflicts)
     int threads; // workgroup size
     size_t lds;  // LDS bytes of the posteriors
-    int hoist = 1;  // specialised kernels: keep gather addresses in registers
+    int hoist = 0;  // specialised kernels: block rows whose gather addresses stay in registers
 };
 
 // Kernel launchers (decode_kernels.hip). Return LDPC_OK or LDPC_EDEVICE.
@@ -81,6 +81,13 @@ void jit_cache_clear();
 // Function `name` of the module built from prelude + source (cached per device).
 int jit_function(const char *tag, const char *src, const std::string &pre, const char *name, hipFunction_t *fn);
 int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what);
+// Default run-time specialised decode layout: one frame per thread (each
+// thread keeps one FP32 message per edge of its check rows), gather
+// addresses kept in registers when they fit beside the messages.
+DecodeLaunch jit_default_launch(const Sched &sc, int path);
+// Bytes of per-lane scratch the specialised decode kernel for this layout
+// needs (register spills); compiles the variant if necessary.
+int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes);
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,

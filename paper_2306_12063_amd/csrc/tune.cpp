@@ -4,6 +4,8 @@
 // registers across iterations -- and keeps the fastest for later calls on
 // that code. The layouts trade registers and LDS per frame against waves
 // per SIMD, which is hard to predict, so they are measured.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -30,20 +32,31 @@ std::string tune_key(const Sched &sc, int path)
     return k;
 }
 
-// Candidate layouts: for each frames-per-thread count, the workgroup shapes
-// whose lanes are at least 85% busy, with and without address hoisting.
+// Candidate layouts: workgroups of at most 256 threads whose lanes are at
+// least 85% busy, one or two frames per thread, and the number of block rows
+// whose gather addresses stay in registers (all, three quarters, half, none).
+// A thread keeps KF messages per edge of its rows in VGPRs, plus an address
+// per hoisted edge; the registers decide how many waves share a SIMD, which
+// is hard to predict, so the candidates are compiled and timed, and those
+// that spill are dropped.
 std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes)
 {
     std::vector<DecodeLaunch> out;
-    for (int KF = 1; KF <= 4; ++KF) {
-        for (int G = 1; G * sc.Z <= kMaxJitThreads; ++G) {
-            DecodeLaunch lc = make_launch(sc, elem_bytes, G, KF, kMaxJitThreads);
+    const int per_row = sc.E / sc.Z;
+    const int hoists[4] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, 0};
+    for (int KF = 1; KF <= 2 && KF * per_row <= 200; ++KF) {
+        for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
+            DecodeLaunch lc = make_launch(sc, elem_bytes, G, KF, kMaxThreads);
             if (lc.G < 1)
                 continue;
             if ((double)(G * sc.Z) / lc.threads < 0.85)
                 continue;
-            for (int hoist = 0; hoist <= 1; ++hoist) {
-                lc.hoist = hoist;
+            int last = -1;
+            for (int h : hoists) {
+                if (h == last || (KF > 1 && h > 0))
+                    continue;
+                last = h;
+                lc.hoist = h;
                 out.push_back(lc);
             }
         }
@@ -78,13 +91,15 @@ void tune_cache_clear()
 int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStream_t stream, DecodeLaunch *best,
                     float *best_ms)
 {
-    const int eb = path == 0 ? 4 : 2;
+    const int eb = 4;   // FP32 posteriors in LDS on both paths
     const size_t in_bytes = (size_t)F * sc.N * (path == 0 ? 4 : 1);
     void *llr = nullptr, *bits = nullptr, *iters = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = LDPC_OK;
     float best_t = 1e30f;
     DecodeLaunch best_lc{};
+    const char *lv = getenv("LDPC_TUNE_LOG");   // set to 1: print every candidate's time
+    const bool log = lv && lv[0] == '1';
     if (hipMalloc(&llr, in_bytes) != hipSuccess || hipMalloc(&bits, (size_t)F * sc.N) != hipSuccess ||
         hipMalloc(&iters, (size_t)F * sizeof(int32_t)) != hipSuccess) {
         rc = fail(LDPC_ENOMEM, "autotune: device allocation failed");
@@ -96,7 +111,16 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         goto done;
     }
     for (const DecodeLaunch &lc : candidates(sc, eb)) {
-        // the first launch compiles the variant and warms the caches
+        size_t scratch = 0;
+        if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch)))
+            goto done;
+        if (scratch > 0) {
+            if (log)
+                fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d spills %zu bytes, skipped\n", lc.G, lc.KF,
+                        lc.hoist, scratch);
+            continue;   // spills registers
+        }
+        // the first launch warms the caches
         rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
                                (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
         if (rc)
@@ -116,6 +140,9 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         float ms = 0.0f;
         hipEventElapsedTime(&ms, e0, e1);
         ms /= reps;
+        if (log)
+            fprintf(stderr, "ldpc autotune: path %d Z %d Mb %d  G %d KF %d threads %d hoisted rows %d  %.4f ms\n", path,
+                    sc.Z, sc.Mb, lc.G, lc.KF, lc.threads, lc.hoist, ms);
         if (ms < best_t) {
             best_t = ms;
             best_lc = lc;
