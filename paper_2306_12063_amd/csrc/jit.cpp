@@ -9,6 +9,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <mutex>
 #include <sstream>
@@ -85,6 +87,64 @@ int rtc_compile(const std::string &src, const std::string &arch, std::string *co
     return LDPC_OK;
 }
 
+// Optional on-disk cache of compiled code objects, so that later processes
+// skip hipRTC: directory from LDPC_JIT_CACHE (unset: no disk cache). The
+// key hashes the architecture, the compiler version and the full source
+// (prelude included), so a changed source never reuses an old object.
+uint64_t fnv1a(const std::string &a, uint64_t h = 1469598103934665603ull)
+{
+    for (unsigned char c : a) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string cache_path(const std::string &src, const std::string &arch)
+{
+    const char *dir = getenv("LDPC_JIT_CACHE");
+    if (!dir || !dir[0])
+        return std::string();
+    int major = 0, minor = 0;
+    hiprtcVersion(&major, &minor);
+    const uint64_t h = fnv1a(src, fnv1a(arch + "|" + std::to_string(major) + "." + std::to_string(minor) + "|"));
+    char name[64];
+    snprintf(name, sizeof(name), "/ldpc_%016llx.co", (unsigned long long)h);
+    return std::string(dir) + name;
+}
+
+bool cache_read(const std::string &path, std::string *code)
+{
+    FILE *f = path.empty() ? nullptr : fopen(path.c_str(), "rb");
+    if (!f)
+        return false;
+    std::string buf;
+    char tmp[65536];
+    size_t n;
+    while ((n = fread(tmp, 1, sizeof(tmp), f)) > 0)
+        buf.append(tmp, n);
+    fclose(f);
+    if (buf.size() < 64)
+        return false;
+    *code = buf;
+    return true;
+}
+
+void cache_write(const std::string &path, const std::string &code)
+{
+    if (path.empty())
+        return;
+    mkdir(getenv("LDPC_JIT_CACHE"), 0755);   // may exist already
+    const std::string tmp = path + "." + std::to_string((long)getpid()) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f)
+        return;
+    const bool ok = fwrite(code.data(), 1, code.size(), f) == code.size();
+    fclose(f);
+    if (!ok || rename(tmp.c_str(), path.c_str()) != 0)
+        remove(tmp.c_str());
+}
+
 int load(const std::string &code, JitKernel *out)
 {
     hipModule_t mod;
@@ -115,9 +175,14 @@ int get_module(const char *tag, const char *src, const std::string &pre, hipModu
     if (colon != std::string::npos)
         arch = arch.substr(0, colon);
     std::string code;
-    int rc = rtc_compile(pre + src, arch, &code);
-    if (rc)
-        return rc;
+    const std::string full = pre + src;
+    const std::string cpath = cache_path(full, arch);
+    int rc;
+    if (!cache_read(cpath, &code)) {
+        if ((rc = rtc_compile(full, arch, &code)))
+            return rc;
+        cache_write(cpath, code);
+    }
     JitKernel k;
     if ((rc = load(code, &k)))
         return rc;
@@ -170,6 +235,21 @@ void jit_cache_clear()
     g_cache.clear();
 }
 
+// Decode kernel of one code: named after its path and shape so that
+// profiles tell the specialised kernels apart.
+static std::string decode_kernel_name(const Sched &sc, int path)
+{
+    return std::string("ldpc_decode_") + (path == 0 ? "f32" : "i8") + "_z" + std::to_string(sc.Z) + "_mb" +
+           std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb);
+}
+
+static int get_decode_function(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn)
+{
+    const std::string name = decode_kernel_name(sc, path);
+    return get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n",
+                        name.c_str(), fn);
+}
+
 DecodeLaunch jit_default_launch(const Sched &sc, int path)
 {
     DecodeLaunch lc = plan_decode(sc, 4, 1);   // FP32 posteriors in LDS on both paths
@@ -182,7 +262,7 @@ DecodeLaunch jit_default_launch(const Sched &sc, int path)
 int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes)
 {
     hipFunction_t fn;
-    int rc = get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode), "ldpc_jit_decode", &fn);
+    int rc = get_decode_function(sc, lc, path, mode, &fn);
     if (rc)
         return rc;
     int v = 0;
@@ -198,7 +278,7 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
                       const int64_t *Fdev)
 {
     hipFunction_t fn;
-    int rc = get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode), "ldpc_jit_decode", &fn);
+    int rc = get_decode_function(sc, lc, path, mode, &fn);
     if (rc)
         return rc;
     long long Fll = (long long)F;
