@@ -24,7 +24,7 @@ struct ldpc_codeset {
     std::vector<int> cls;              // class of each code
     std::vector<int> class_rep;        // a code of each class
     int cmb = 0, cd = 0;               // largest block-row count and degree
-    // per arithmetic path (0 FP32, 1 int16 posteriors): device tables
+    // per arithmetic path (0 FP32, 1 fixed point): device tables
     void *d_codes[2] = {nullptr, nullptr};
     void *d_etab[2] = {nullptr, nullptr};
     size_t lds_elems[2] = {0, 0};
@@ -53,15 +53,9 @@ bool same_structure(const Sched &a, const Sched &b)
     return true;
 }
 
-int fwp_for(int G, int path)
-{
-    int FWp = G;
-    if (path == 0)
-        return FWp | 1;
-    while (FWp % 4 != 2)
-        ++FWp;
-    return FWp;
-}
+// odd dword stride: consecutive rows of a frame hit distinct LDS banks (the
+// posteriors are FP32 in LDS on both paths)
+int fwp_for(int G) { return G | 1; }
 
 std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 {
@@ -133,20 +127,20 @@ int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, cons
         size_t lds = 0;
         for (int c = 0; c < n; ++c) {
             const Sched &s = cs->sc[c];
-            const int G = cs->G[c], FWp = fwp_for(G, path);
-            const size_t bytes = (size_t)s.N * FWp * (path == 0 ? 4 : 2);
+            const int G = cs->G[c], FWp = fwp_for(G);
+            const size_t bytes = (size_t)(s.N + s.Z) * FWp * 4;   // one column block of padding
             if (bytes > (size_t)kLdsBudget) {
                 ldpc_codeset_destroy(cs);
                 return fail(LDPC_ERANGE, "code %d (N=%d) does not fit the batched kernel's LDS budget", c, s.N);
             }
-            lds = std::max(lds, (size_t)s.N * FWp);
+            lds = std::max(lds, (size_t)(s.N + s.Z) * FWp);
             rec[c] = CodeRec{s.Z, s.N, cs->cls[c], G, FWp, (int)(etab.size() / 2), 0, 0};
             for (int i = 0; i < cs->cmb; ++i)
                 for (int e = 0; e < cs->cd; ++e) {
                     int base = 0, thr = 1 << 30;
                     if (i < s.Mb && e < s.deg[i]) {
                         const int col = (int)(s.edge[i][e] >> 16), sh = (int)(s.edge[i][e] & 0xffffu);
-                        base = (col * s.Z + sh) * FWp;
+                        base = (col * s.Z + sh) * FWp * 4;
                         thr = s.Z - sh;
                     }
                     etab.push_back(base);
