@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--frames", type=int, default=1 << 16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the default decode layout")
+    ap.add_argument("--no-mixed-batch", action="store_true",
+                    help="skip the secondary mixed-code batch measurement (114 codes, one persistent launch)")
+    ap.add_argument("--batch-frames", type=int, default=1 << 18)
     ap.add_argument("--cpu-frames", type=int, default=12288,
                     help="frames per rate and path in the CPU-oracle baseline sample")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -113,6 +116,78 @@ def cpu_baseline(cases, nframes):
     return {"value": bits / dt / 1e9, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
             "sample": f"{nframes} frames per rate and path (FP32 and int8, 4 rates, Z=81), "
                       f"{ITERS} fixed iterations, {dt:.1f} s wall"}
+
+
+def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
+    """Frames of all 114 WiMAX-shaped codes (6 rate classes x Z = 24..96) in
+    one persistent launch: code ids uniform, ragged lengths, Eb/N0 2 dB.
+    Untimed: frame generation and the batch layout autotuner. Timed: `steps`
+    FP32 and int8 decodes at 10 fixed iterations, then with early termination."""
+    import synth
+    codes = synth.wimax_code_set()
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    rng = np.random.default_rng(seed)
+    cid = rng.integers(0, len(codes), frames).astype(np.int32)
+    Ns = np.array([h.shape[1] * Z for _, Z, h in codes])
+    Ks = np.array([(h.shape[1] - h.shape[0]) * Z for _, Z, h in codes])
+    Es = np.array([int((h >= 0).sum()) * Z for _, Z, h in codes])
+    off = np.zeros(frames, np.int64)
+    off[1:] = np.cumsum(Ns[cid])[:-1]
+    total, kbits, edges = int(Ns[cid].sum()), int(Ks[cid].sum()), int(Es[cid].sum())
+    d_off = torch.from_numpy(off).to(dev)
+    d_cid = torch.from_numpy(cid).to(dev)
+    llr = torch.empty(total, dtype=torch.float32, device=dev)
+    for c in range(len(codes)):
+        idx = np.flatnonzero(cid == c)
+        if len(idx) == 0:
+            continue
+        _, Z, h = codes[c]
+        N, K = h.shape[1] * Z, (h.shape[1] - h.shape[0]) * Z
+        s2 = synth.sigma2_from_ebn0(EBN0_DB, K / N)
+        cw = P.ldpc_encode(h, Z, P.ldpc_random_bits(seed + 10 * c, len(idx), K, device=dev))
+        lc = P.ldpc_awgn_llr(seed + 10 * c + 1, cw, float(np.sqrt(s2)), 2.0 / s2)
+        pos = (d_off[torch.from_numpy(idx).to(dev)][:, None] + torch.arange(N, device=dev)[None, :]).reshape(-1)
+        llr[pos] = lc.reshape(-1)
+    q = P.ldpc_quantize_i8(llr)
+    work = torch.empty(cs.work_bytes(frames), dtype=torch.uint8, device=dev)
+    bits = torch.empty(total, dtype=torch.uint8, device=dev)
+    iters = torch.empty(frames, dtype=torch.int32, device=dev)
+    ok = torch.empty(frames, dtype=torch.uint8, device=dev)
+    layouts = {"f32": cs.autotune("f32", d_cid, d_off, llr, max_iter=ITERS, work=work),
+               "i8": cs.autotune("i8", d_cid, d_off, q, max_iter=ITERS, work=work)}
+    res = {}
+    stream = torch.cuda.current_stream()
+    for path in ("f32", "i8"):
+        for et in (False, True):
+            def run():
+                if path == "f32":
+                    cs.decode_f32(d_cid, d_off, llr, max_iter=ITERS, alpha=ALPHA, early_term=et, bits=bits,
+                                  iters=iters, ok=ok, work=work, want_post=False)
+                else:
+                    cs.decode_i8(d_cid, d_off, q, max_iter=ITERS, offset=OFFSET, early_term=et, bits=bits,
+                                 iters=iters, ok=ok, work=work, want_post=False)
+            run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            key = f"{path}{'_et' if et else ''}"
+            res[key] = {"ms": round(ms, 4), "gbit_s": round(kbits / (ms / 1e3) / 1e9, 3),
+                        "mean_iters": round(float(iters.float().mean()), 3),
+                        "fer_syndrome": round(1.0 - float(ok.float().mean()), 4)}
+            if not et:
+                tops = ALG_OPS_PER_EDGE_ITER * edges * ITERS / (ms / 1e3) / 1e12
+                res[key]["valu_tops"] = round(tops, 3)
+                res[key]["alu_frac"] = round(tops / PEAK_VALU_TOPS, 4)
+    return {"workload": f"114 WiMAX-shaped synthetic codes (rate classes 1/2 2/3A 2/3B 3/4A 3/4B 5/6, "
+                        f"Z=24..96, N=576..2304), {frames} frames with uniform code ids in one persistent "
+                        f"launch, Eb/N0={EBN0_DB} dB, FP32 NMS alpha={ALPHA} / int8 OMS offset={OFFSET}, "
+                        f"{ITERS} iterations (fixed; _et: early termination)",
+            "info_bits": kbits, "layouts": layouts, **res}
 
 
 def main():
@@ -224,6 +299,8 @@ def main():
         "per_kernel": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()
                         if k not in ("alg_ops", "hbm_bytes")} for p in per],
     }
+    if not args.no_mixed_batch:
+        out["mixed_batch"] = mixed_batch(P, torch, dev, args.steps, args.batch_frames)
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -243,6 +243,22 @@ int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const i
                          int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
 
 /*
+ * Batch layout autotuner (frames per work item and workgroup size of the
+ * persistent kernel). Decodes the caller's batch -- same arguments as
+ * ldpc_decode_batch_f32/_i8 for `path` 0/1 -- with alpha 0.75 (FP32) or
+ * offset 1 (int8), early termination off, under each candidate layout:
+ * workgroups of 256 or 512 threads, each code's work items holding
+ * floor(threads / Z) or half as many frames (at most 64). Keeps the fastest
+ * for later batched decodes of `path` with this code set; out[2] receives
+ * {threads, divisor} and *ms its time per decode. bits and iters receive the
+ * last decode's results. Synchronises `stream`; the code set must not be in
+ * use on another stream meanwhile (its tables are rebuilt).
+ */
+int ldpc_codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
+                          int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, size_t work_bytes,
+                          int32_t out[2], float *ms, void *stream);
+
+/*
  * int8 quantiser for channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rounding half to even. llr: device f32 [n], q: device i8 [n].
  */

@@ -51,6 +51,7 @@ EXPORTS = {
     "ldpc_decode_batch_f32": ([_p, _p, _p, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p], _i32),
     "ldpc_decode_batch_i8": ([_p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p],
                              _i32),
+    "ldpc_codeset_autotune": ([_p, _i32, _p, _p, _p, _i64, _i32, _p, _p, _p, C.c_size_t, _p, _p, _p], _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -397,6 +398,27 @@ class Codeset:
         return self._decode("ldpc_decode_batch_f32", code_id, off, llr, llr.numel(), code_id.numel(),
                             (int(max_iter), float(alpha), int(bool(early_term))), bits, post, iters, ok, work, stream,
                             torch.float32, torch.float32, want_post)
+
+    def autotune(self, path, code_id, off, llr, max_iter=10, work=None, stream=None):
+        """Times the batch layouts on this batch (ldpc_codeset_autotune) and keeps
+        the fastest for `path` ("f32" or "i8"). Returns dict(threads, divisor, ms)."""
+        torch = _torch()
+        F = code_id.numel()
+        p = {"f32": 0, "i8": 1}[path]
+        dev = llr.device
+        work = torch.empty(self.work_bytes(F), dtype=torch.uint8, device=dev) if work is None else work
+        bits = torch.empty(llr.numel(), dtype=torch.uint8, device=dev)
+        iters = torch.empty(F, dtype=torch.int32, device=dev)
+        out = np.zeros(2, np.int32)
+        ms = C.c_float()
+        _check(lib().ldpc_codeset_autotune(self._cs, p, _dev(code_id, torch.int32, "code_id", (F,)),
+                                           _dev(off, torch.int64, "off", (F,)),
+                                           _dev(llr, torch.float32 if p == 0 else torch.int8, "llr"), F,
+                                           int(max_iter), _dev(bits, torch.uint8, "bits"),
+                                           _dev(iters, torch.int32, "iters"), _dev(work, torch.uint8, "work"),
+                                           work.numel(), out.ctypes.data_as(C.c_void_p), C.byref(ms),
+                                           _stream(stream)), "ldpc_codeset_autotune")
+        return dict(threads=int(out[0]), divisor=int(out[1]), ms=float(ms.value))
 
     def decode_i8(self, code_id, off, llr, max_iter=10, offset=1, wq=0, early_term=True, bits=None, post=None,
                   iters=None, ok=None, work=None, want_post=True, stream=None):

@@ -8,6 +8,8 @@
 // five stream-ordered kernels (clear, histogram by code, plan of work items,
 // scatter of frame indices, persistent decode) with no host synchronisation,
 // so a caller may capture it in a hipGraph.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -24,11 +26,13 @@ struct ldpc_codeset {
     std::vector<int> cls;              // class of each code
     std::vector<int> class_rep;        // a code of each class
     int cmb = 0, cd = 0;               // largest block-row count and degree
-    // per arithmetic path (0 FP32, 1 fixed point): device tables
+    // per arithmetic path (0 FP32, 1 fixed point): layout and device tables
+    int threads[2] = {256, 256};       // workgroup size of the persistent kernel
+    int gdiv[2] = {1, 1};              // frames per item = floor(threads / Z) / gdiv (at most 64)
     void *d_codes[2] = {nullptr, nullptr};
     void *d_etab[2] = {nullptr, nullptr};
     size_t lds_elems[2] = {0, 0};
-    std::vector<int> G;                // frames per work item of each code
+    std::vector<int> G[2];             // frames per work item of each code
 };
 
 namespace ldpc {
@@ -61,7 +65,7 @@ std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 {
     std::ostringstream o;
     const int nclass = (int)cs.class_rep.size();
-    o << "#define LDPC_THREADS " << kMaxThreads << "\n#define LDPC_LDS " << cs.lds_elems[path]
+    o << "#define LDPC_THREADS " << cs.threads[path] << "\n#define LDPC_LDS " << cs.lds_elems[path]
       << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n#define LDPC_NCLASS " << nclass
       << "\n#define LDPC_CMB " << cs.cmb << "\n#define LDPC_CD " << cs.cd << "\n";
     o << "__device__ constexpr int kMBc[" << nclass << "] = {";
@@ -85,6 +89,64 @@ std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 }  // namespace
 
 extern const char kJitBatchSource[];
+
+// (Re)builds a path's device tables for a layout: workgroups of `threads`
+// threads, floor(threads / Z) / gdiv frames per work item (at most 64).
+int build_tables(ldpc_codeset *cs, int path, int threads, int gdiv)
+{
+    const int n = cs->ncodes;
+    std::vector<CodeRec> rec(n);
+    std::vector<int> etab, G(n);
+    size_t lds = 0;
+    for (int c = 0; c < n; ++c) {
+        const Sched &s = cs->sc[c];
+        G[c] = std::max(1, std::min(64, threads / s.Z) / gdiv);
+        // fewer frames per item where the posteriors (one column block of
+        // padding included) would not fit the LDS budget
+        while (G[c] > 1 && (size_t)(s.N + s.Z) * fwp_for(G[c]) * 4 > (size_t)kLdsBudget)
+            --G[c];
+        const int FWp = fwp_for(G[c]);
+        if ((size_t)(s.N + s.Z) * FWp * 4 > (size_t)kLdsBudget)
+            return fail(LDPC_ERANGE, "code %d (N=%d) does not fit the batched kernel's LDS budget", c, s.N);
+        lds = std::max(lds, (size_t)(s.N + s.Z) * FWp);
+        rec[c] = CodeRec{s.Z, s.N, cs->cls[c], G[c], FWp, (int)(etab.size() / 2), 0, 0};
+        for (int i = 0; i < cs->cmb; ++i)
+            for (int e = 0; e < cs->cd; ++e) {
+                int base = 0, thr = 1 << 30;
+                if (i < s.Mb && e < s.deg[i]) {
+                    const int col = (int)(s.edge[i][e] >> 16), sh = (int)(s.edge[i][e] & 0xffffu);
+                    base = (col * s.Z + sh) * FWp * 4;
+                    thr = s.Z - sh;
+                }
+                etab.push_back(base);
+                etab.push_back(thr);
+            }
+    }
+    void *dc = nullptr, *de = nullptr;
+    if (hipMalloc(&dc, rec.size() * sizeof(CodeRec)) != hipSuccess ||
+        hipMalloc(&de, etab.size() * sizeof(int)) != hipSuccess) {
+        if (dc)
+            (void)hipFree(dc);
+        return fail(LDPC_ENOMEM, "code set: device allocation failed");
+    }
+    if (hipMemcpy(dc, rec.data(), rec.size() * sizeof(CodeRec), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(de, etab.data(), etab.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dc);
+        (void)hipFree(de);
+        return fail(LDPC_EDEVICE, "code set: copy to device failed");
+    }
+    if (cs->d_codes[path])
+        (void)hipFree(cs->d_codes[path]);
+    if (cs->d_etab[path])
+        (void)hipFree(cs->d_etab[path]);
+    cs->d_codes[path] = dc;
+    cs->d_etab[path] = de;
+    cs->lds_elems[path] = lds;
+    cs->threads[path] = threads;
+    cs->gdiv[path] = gdiv;
+    cs->G[path] = G;
+    return LDPC_OK;
+}
 
 int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, const int *Z, int n, ldpc_codeset **out)
 {
@@ -110,55 +172,20 @@ int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, cons
         cs->cls.push_back(k);
         cs->cmb = std::max(cs->cmb, cs->sc[c].Mb);
         cs->cd = std::max(cs->cd, cs->sc[c].dmax);
-        const int G = std::min(64, kMaxThreads / cs->sc[c].Z);
-        if (G < 1) {
+        if (cs->sc[c].Z > kMaxThreads) {
             delete cs;
             return fail(LDPC_ERANGE, "code %d: Z=%d exceeds the batched kernel's workgroup", c, Z[c]);
         }
-        cs->G.push_back(G);
     }
     if (hipGetDevice(&cs->device) != hipSuccess) {
         delete cs;
         return fail(LDPC_EDEVICE, "hipGetDevice failed");
     }
     for (int path = 0; path < 2; ++path) {
-        std::vector<CodeRec> rec(n);
-        std::vector<int> etab;
-        size_t lds = 0;
-        for (int c = 0; c < n; ++c) {
-            const Sched &s = cs->sc[c];
-            const int G = cs->G[c], FWp = fwp_for(G);
-            const size_t bytes = (size_t)(s.N + s.Z) * FWp * 4;   // one column block of padding
-            if (bytes > (size_t)kLdsBudget) {
-                ldpc_codeset_destroy(cs);
-                return fail(LDPC_ERANGE, "code %d (N=%d) does not fit the batched kernel's LDS budget", c, s.N);
-            }
-            lds = std::max(lds, (size_t)(s.N + s.Z) * FWp);
-            rec[c] = CodeRec{s.Z, s.N, cs->cls[c], G, FWp, (int)(etab.size() / 2), 0, 0};
-            for (int i = 0; i < cs->cmb; ++i)
-                for (int e = 0; e < cs->cd; ++e) {
-                    int base = 0, thr = 1 << 30;
-                    if (i < s.Mb && e < s.deg[i]) {
-                        const int col = (int)(s.edge[i][e] >> 16), sh = (int)(s.edge[i][e] & 0xffffu);
-                        base = (col * s.Z + sh) * FWp * 4;
-                        thr = s.Z - sh;
-                    }
-                    etab.push_back(base);
-                    etab.push_back(thr);
-                }
-        }
-        cs->lds_elems[path] = lds;
-        if (hipMalloc(&cs->d_codes[path], rec.size() * sizeof(CodeRec)) != hipSuccess ||
-            hipMalloc(&cs->d_etab[path], etab.size() * sizeof(int)) != hipSuccess) {
+        int rc = build_tables(cs, path, kMaxThreads, 1);
+        if (rc) {
             ldpc_codeset_destroy(cs);
-            return fail(LDPC_ENOMEM, "code set: device allocation failed");
-        }
-        if (hipMemcpy(cs->d_codes[path], rec.data(), rec.size() * sizeof(CodeRec), hipMemcpyHostToDevice) !=
-                hipSuccess ||
-            hipMemcpy(cs->d_etab[path], etab.data(), etab.size() * sizeof(int), hipMemcpyHostToDevice) !=
-                hipSuccess) {
-            ldpc_codeset_destroy(cs);
-            return fail(LDPC_EDEVICE, "code set: copy to device failed");
+            return rc;
         }
     }
     *out = cs;
@@ -203,7 +230,7 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
         return rc;
     // persistent grid: as many workgroups as can be resident at once
     int per_cu = 0, cus = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f_dec, kMaxThreads, 0) != hipSuccess ||
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f_dec, cs->threads[path], 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cs->device) != hipSuccess)
         return fail(LDPC_EDEVICE, "occupancy query failed");
     const unsigned grid = (unsigned)std::max(1, per_cu * cus);
@@ -212,7 +239,67 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
     void *a_dec[] = {(void *)&items, (void *)&nitems, (void *)&queue, (void *)&perm, (void *)&off, (void *)&codes,
                      (void *)&etab, (void *)&llr, (void *)&max_iter, (void *)&alpha, (void *)&offset, (void *)&wq,
                      (void *)&et, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
-    return jit_launch(f_dec, grid, kMaxThreads, stream, a_dec, "batch decode");
+    return jit_launch(f_dec, grid, cs->threads[path], stream, a_dec, "batch decode");
+}
+
+// Times the batched decode of the caller's batch for each candidate layout
+// and keeps the fastest (tables rebuilt for it).
+int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
+                     int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, hipStream_t stream,
+                     int32_t out[2], float *best_ms)
+{
+    static const int cand[4][2] = {{256, 1}, {512, 1}, {256, 2}, {512, 2}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return fail(LDPC_EDEVICE, "autotune: hipEventCreate failed");
+    }
+    int rc = LDPC_OK, best = -1;
+    float best_t = 1e30f;
+    const char *lv = getenv("LDPC_TUNE_LOG");
+    const bool log = lv && lv[0] == '1';
+    for (int k = 0; k < 4 && rc == LDPC_OK; ++k) {
+        if ((rc = build_tables(cs, path, cand[k][0], cand[k][1])))
+            break;
+        auto run = [&]() {
+            return launch_batch_decode(cs, path, 0, code_id, off, llr, F, max_iter, 0.75f, 1, 0, 0, bits, nullptr,
+                                       iters, nullptr, work, stream);
+        };
+        if ((rc = run()))   // compiles the variant and warms the caches
+            break;
+        hipEventRecord(e0, stream);
+        for (int r = 0; r < 3 && rc == LDPC_OK; ++r)
+            rc = run();
+        hipEventRecord(e1, stream);
+        if (rc)
+            break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(LDPC_EDEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= 3;
+        if (log)
+            fprintf(stderr, "ldpc batch autotune: path %d threads %d frames/item divisor %d  %.4f ms\n", path,
+                    cand[k][0], cand[k][1], ms);
+        if (ms < best_t) {
+            best_t = ms;
+            best = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best >= 0) {
+        const int brc = build_tables(cs, path, cand[best][0], cand[best][1]);
+        if (rc == LDPC_OK)
+            rc = brc;
+        out[0] = cand[best][0];
+        out[1] = cand[best][1];
+        *best_ms = best_t;
+    }
+    return rc;
 }
 
 }  // namespace ldpc
@@ -255,7 +342,7 @@ int ldpc_codeset_info(const ldpc_codeset *cs, int code, int64_t out[8])
     out[3] = s.E;
     out[4] = s.dmax;
     out[5] = cs->cls[code];
-    out[6] = cs->G[code];
+    out[6] = cs->G[0][code];
     out[7] = (int64_t)cs->class_rep.size();
     return LDPC_OK;
 }
@@ -309,6 +396,21 @@ int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const i
         return fail(LDPC_EINVAL, "offset must be in [0, 127] and wq in [0, 31]");
     return launch_batch_decode(cs, 1, wq > 0 ? 1 : 0, code_id, off, llr, F, max_iter, 0.0f, offset, wq, early_term,
                                bits, post, iters, ok, work, (hipStream_t)stream);
+}
+
+int ldpc_codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
+                          int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, size_t work_bytes,
+                          int32_t out[2], float *ms, void *stream)
+{
+    if (path != 0 && path != 1)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    if (rc)
+        return rc;
+    if (F == 0 || !out || !ms)
+        return fail(LDPC_EINVAL, "autotune needs a non-empty batch and output pointers");
+    return codeset_autotune(cs, path, code_id, off, llr, F, max_iter, bits, iters, work, (hipStream_t)stream, out,
+                            ms);
 }
 
 }  // extern "C"

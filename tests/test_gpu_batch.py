@@ -142,3 +142,35 @@ def test_batch_full_size_sampled(wimax_set):
         wb, wp, wi, _ = oracle.decode_f32(h, Z, lh[off[f]:off[f] + N][None], max_iter=10, early_term=False)
         assert np.array_equal(bh[off[f]:off[f] + N], wb[0]) and np.array_equal(ph[off[f]:off[f] + N], wp[0])
         assert ih[f] == wi[0]
+
+
+def test_batch_autotune_keeps_parity():
+    # the tuner rebuilds the code set's tables for each layout; the chosen
+    # layout must still decode every frame exactly as the oracle does
+    all_codes = synth.wimax_code_set()
+    codes = [all_codes[k] for k in range(0, len(all_codes), 10)]
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    F = 160
+    cid, off, llr, total, per = _ragged(codes, F, 2.5, 17)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    q = oracle.quantize_i8(llr)
+    for path in ("f32", "i8"):
+        src = d(llr) if path == "f32" else d(q)
+        cfg = cs.autotune(path, d(cid), d(off), src, max_iter=6)
+        assert cfg["threads"] in (256, 512) and cfg["divisor"] in (1, 2) and cfg["ms"] > 0
+        if path == "f32":
+            bits, post, iters, ok = cs.decode_f32(d(cid), d(off), src, max_iter=6, alpha=0.75, early_term=True)
+        else:
+            bits, post, iters, ok = cs.decode_i8(d(cid), d(off), src, max_iter=6, offset=1, early_term=True)
+        torch.cuda.synchronize()
+        bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+        for c, (idx, l) in per.items():
+            _, Z, h = codes[c]
+            N = 24 * Z
+            if path == "f32":
+                wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+            else:
+                wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=6, offset=1, early_term=True)
+            for k, f in enumerate(idx):
+                assert np.array_equal(bits[off[f]:off[f] + N], wb[k]) and np.array_equal(post[off[f]:off[f] + N], wp[k])
+            assert np.array_equal(iters[idx], wi)
