@@ -43,27 +43,52 @@ def make_frames(hbm, Z, F, ebn0_db, seed, device="cuda"):
     return bits, cw, llr
 
 
+def iteration_weights(kind, T, device="cuda"):
+    """Weights of the per-iteration losses in the training objective:
+    'uniform' (the mean over iterations), 'ramp' (proportional to t + 1) or
+    'last' (the last iteration only); each sums to one."""
+    if kind == "uniform":
+        g = torch.ones(T)
+    elif kind == "ramp":
+        g = torch.arange(1, T + 1, dtype=torch.float32)
+    elif kind == "last":
+        g = torch.zeros(T)
+        g[-1] = 1.0
+    else:
+        raise ValueError(kind)
+    return (g * (T / g.sum())).to(device)
+
+
 def train(hbm, Z, T=10, frames=1 << 20, batch=4096, lr=1e-2, ebn0_range=(1.0, 4.0), seed=1, w0=0.75,
-          device="cuda", log_every=0):
+          device="cuda", log_every=0, lr_final=None, tie="none", iter_loss="uniform"):
     """Trains w [T][Mb][Nb] with Adam on fresh frames (Eb/N0 uniform per frame)
-    through the kernels' forward and adjoint. Returns (w, loss history)."""
+    through the kernels' forward and adjoint. lr_final: if given, the step
+    size follows a cosine from lr down to lr_final. tie='layer' shares one
+    weight per (iteration, block row). iter_loss weights the per-iteration
+    losses (iteration_weights). Returns (w, loss history)."""
     Mb, Nb = np.asarray(hbm).shape
-    w = torch.full((T, Mb, Nb), w0, dtype=torch.float32, device=device, requires_grad=True)
-    opt = torch.optim.Adam([w], lr=lr)
+    shape = (T, Mb, 1) if tie == "layer" else (T, Mb, Nb)
+    p = torch.full(shape, w0, dtype=torch.float32, device=device, requires_grad=True)
+    gam = iteration_weights(iter_loss, T, device)
+    opt = torch.optim.Adam([p], lr=lr)
     rng = np.random.default_rng(seed)
     history = []
     steps = max(1, frames // batch)
     for step in range(steps):
+        if lr_final is not None:
+            for gr in opt.param_groups:
+                gr["lr"] = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / steps))
         e = rng.uniform(ebn0_range[0], ebn0_range[1], batch)
         _, cw, llr = make_frames(hbm, Z, batch, e, seed * 1000003 + step, device)
         opt.zero_grad(set_to_none=True)
-        loss = nms_loss(w, llr, cw, hbm, Z).sum()
-        loss.backward()
+        w = p.expand(T, Mb, Nb)
+        per_iter = nms_loss(w, llr, cw, hbm, Z)
+        (per_iter * gam).sum().backward()
         opt.step()
-        history.append(float(loss.detach()))
+        history.append(float(per_iter.detach().sum()))
         if log_every and (step % log_every == 0 or step == steps - 1):
             print(f"  step {step:4d}/{steps}  loss {history[-1]:.5f}", flush=True)
-    return w.detach(), history
+    return p.detach().expand(T, Mb, Nb).contiguous(), history
 
 
 class _Dec:
@@ -155,12 +180,14 @@ def iters_at(points, ebn0):
     return p["mean_iters"]
 
 
-def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, seed=1, log_every=0):
+def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, seed=1, log_every=0,
+            train_range=(1.0, 4.0), lr=1e-2, lr_final=None, tie="none", iter_loss="uniform"):
     """Trains a weight set for one code and compares the three decoder forms."""
     if ebn0_list is None:
         ebn0_list = [1.0 + 0.25 * k for k in range(21)]
     t0 = time.perf_counter()
-    w, hist = train(hbm, Z, frames=train_frames, seed=seed, log_every=log_every)
+    w, hist = train(hbm, Z, frames=train_frames, seed=seed, log_every=log_every, ebn0_range=train_range, lr=lr,
+                    lr_final=lr_final, tie=tie, iter_loss=iter_loss)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     res = sweep(hbm, Z, decoders(hbm, Z, w), ebn0_list, eval_frames, seed=seed + 1)
@@ -176,7 +203,10 @@ def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, s
         for name in summary:
             it = summary[name]["mean_iters_at_plain_point"]
             summary[name]["iter_reduction"] = (None if it is None or base == 0 else 1.0 - it / base)
-    return dict(train_seconds=t_train, loss_first=hist[0], loss_last=hist[-1], summary=summary, sweep=res)
+    return dict(train_seconds=t_train, loss_first=hist[0], loss_last=float(np.mean(hist[-16:])),
+                train_range=list(train_range), lr=lr, lr_final=lr_final, tie=tie, iter_loss=iter_loss,
+                summary=summary, sweep=res,
+                weights=w.cpu().numpy().round(5).tolist())
 
 
 def _code(spec):
@@ -192,11 +222,20 @@ def main():
     ap.add_argument("--eval-frames", type=int, default=1 << 18)
     ap.add_argument("--ebn0", default="1:6:0.25", help="start:stop:step in dB")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--train-ebn0", default="1:4", help="lo:hi, per-frame uniform training Eb/N0 in dB")
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--lr-final", type=float, default=None, help="cosine decay of the step size to this value")
+    ap.add_argument("--tie", choices=["none", "layer"], default="none",
+                    help="layer: one weight per (iteration, block row)")
+    ap.add_argument("--iter-loss", choices=["uniform", "ramp", "last"], default="uniform",
+                    help="weights of the per-iteration losses in the objective")
     args = ap.parse_args()
     a, b, s = (float(x) for x in args.ebn0.split(":"))
     pts = list(np.round(np.arange(a, b + 1e-9, s), 4))
+    lo, hi = (float(x) for x in args.train_ebn0.split(":"))
     hbm, Z = _code(args.code)
-    r = compare(hbm, Z, args.train_frames, args.eval_frames, pts, args.seed, log_every=32)
+    r = compare(hbm, Z, args.train_frames, args.eval_frames, pts, args.seed, log_every=64, train_range=(lo, hi),
+                lr=args.lr, lr_final=args.lr_final, tie=args.tie, iter_loss=args.iter_loss)
     r["code"] = args.code
     print(json.dumps(r), flush=True)
 
