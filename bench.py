@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-mixed-batch", action="store_true",
                     help="skip the secondary mixed-code batch measurement (114 codes, one persistent launch)")
     ap.add_argument("--batch-frames", type=int, default=1 << 18)
-    ap.add_argument("--cpu-frames", type=int, default=12288,
+    ap.add_argument("--cpu-frames", type=int, default=32768,
                     help="frames per rate and path in the CPU-oracle baseline sample")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (a reference kernel "

@@ -245,3 +245,22 @@ def test_full_batch_sampled(rate):
     assert np.array_equal(q_s, oracle.quantize_i8(l_s))
     want_q = oracle.decode_i8(h, 81, q_s, max_iter=10, offset=1, early_term=False)
     _assert_exact(tuple(t[tidx] for t in (bq, pq, iq, oq)), want_q)
+
+
+@pytest.mark.parametrize("rate,Z", [("1/2", 27), ("5/6", 81), ("2/3", 81)])
+def test_precompiled_kernels_match_oracle(rate, Z, monkeypatch):
+    # LDPC_JIT=0 selects the precompiled per-shape kernels instead of the
+    # run-time specialised ones (the library reads the switch on every call)
+    monkeypatch.setenv("LDPC_JIT", "0")
+    h = synth.wifi_code(rate, Z)
+    _, _, llr = _frames(h, Z, 77, 2.5 if rate == "1/2" else 4.0, 23)
+    for et in (True, False):
+        got, want = _decode_f32_both(h, Z, llr, max_iter=8, alpha=0.75, early_term=et)
+        gp, wp = _assert_f32_parity(got, want)
+        assert np.array_equal(gp, wp)
+        q = oracle.quantize_i8(llr)
+        gb, gpost, gi, go = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=8, offset=1, early_term=et)
+        wb, wpost, wi, wo = oracle.decode_i8(h, Z, q, max_iter=8, offset=1, early_term=et)
+        torch.cuda.synchronize()
+        assert np.array_equal(gb.cpu().numpy(), wb) and np.array_equal(gpost.cpu().numpy(), wpost)
+        assert np.array_equal(gi.cpu().numpy(), wi) and np.array_equal(go.cpu().numpy(), wo)
