@@ -49,6 +49,9 @@ def lib():
                 "orc_decode_f32": [p, i32, i32, i32, p, i64, i32, f32, i32, p, p, p, p, p],
                 "orc_decode_f64": [p, i32, i32, i32, p, i64, i32, f64, i32, p, p, p, p, p],
                 "orc_decode_i8": [p, i32, i32, i32, p, i64, i32, i32, i32, p, i32, p, p, p, p],
+                "orc_decode_flood_f32": [p, i32, i32, i32, p, i64, i32, f32, i32, p, p, p, p],
+                "orc_decode_flood_f64": [p, i32, i32, i32, p, i64, i32, f64, i32, p, p, p, p],
+                "orc_decode_flood_i8": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
                 "orc_quantize_i8": [p, p, i64, f32],
                 "orc_nms_train": [p, i32, i32, i32, p, p, i64, i32, p, i32, p, p, p],
                 "orc_frame_bits": [u64, i64, i64, p],
@@ -165,6 +168,52 @@ def decode_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, wq_table=None, early_ter
     _check(lib().orc_decode_i8(_ptr(h), Mb, Nb, Z, _ptr(llr), F, max_iter, offset, wq, _ptr(wq_table),
                                int(bool(early_term)), _ptr(bits), _ptr(post), _ptr(iters), _ptr(ok)),
            "decode_i8")
+    return bits, post, iters, ok
+
+
+def _flood_fp(fn, dtype, hbm, Z, llr, max_iter, alpha, early_term):
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    llr = np.ascontiguousarray(llr, dtype=dtype)
+    F, N = llr.shape
+    if N != Nb * Z:
+        raise ValueError("llr has the wrong length")
+    bits = np.zeros((F, N), np.uint8)
+    post = np.zeros((F, N), dtype)
+    iters = np.zeros(F, np.int32)
+    ok = np.zeros(F, np.uint8)
+    _check(fn(_ptr(h), Mb, Nb, Z, _ptr(llr), F, max_iter, alpha, int(bool(early_term)), _ptr(bits), _ptr(post),
+              _ptr(iters), _ptr(ok)), "decode_flood")
+    return bits, post, iters, ok
+
+
+def decode_flood_f32(hbm, Z, llr, max_iter=10, alpha=0.75, early_term=True):
+    """Flooding (two-phase) normalised min-sum in float (Sec. 4, eqs. 18-23
+    without layering). Returns (bits, posteriors f32, iterations, ok)."""
+    return _flood_fp(lib().orc_decode_flood_f32, np.float32, hbm, Z, llr, max_iter, alpha, early_term)
+
+
+def decode_flood_f64(hbm, Z, llr, max_iter=10, alpha=0.75, early_term=True):
+    """The flooding decoder evaluated in double."""
+    return _flood_fp(lib().orc_decode_flood_f64, np.float64, hbm, Z, llr, max_iter, alpha, early_term)
+
+
+def decode_flood_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, early_term=True):
+    """Flooding schedule on the saturating fixed-point path (int8 LLRs and
+    messages, int16 posteriors). Returns (bits, posteriors i16, iterations, ok)."""
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    llr = np.ascontiguousarray(llr, dtype=np.int8)
+    F, N = llr.shape
+    if N != Nb * Z:
+        raise ValueError("llr has the wrong length")
+    bits = np.zeros((F, N), np.uint8)
+    post = np.zeros((F, N), np.int16)
+    iters = np.zeros(F, np.int32)
+    ok = np.zeros(F, np.uint8)
+    _check(lib().orc_decode_flood_i8(_ptr(h), Mb, Nb, Z, _ptr(llr), F, max_iter, offset, wq,
+                                     int(bool(early_term)), _ptr(bits), _ptr(post), _ptr(iters), _ptr(ok)),
+           "decode_flood_i8")
     return bits, post, iters, ok
 
 

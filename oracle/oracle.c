@@ -409,6 +409,104 @@ int orc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, 
     return ORC_OK;
 }
 
+/*
+ * Flooding schedule on the saturating fixed-point path: the check phase is
+ * that of orc_decode_i8 (int8 messages, |Q| clipped to 127, offset or wq/16
+ * magnitude rule), all rows reading the posteriors of the previous
+ * iteration; the variable phase is Z[n] = sat16(... sat16(Z0[n] + R_a) + R_b
+ * ...), the new messages at n added in ascending block-row order (eq. 20).
+ */
+int orc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                        int offset, int wq, int early_term, uint8_t *bits, int16_t *post, int32_t *iters,
+                        uint8_t *ok)
+{
+    if (check_base(hbm, Mb, Nb, Z, 1) || F < 0 || max_iter < 1 || offset < 0 || offset > 127 ||
+        wq < 0 || wq > 31)
+        return ORC_EINVAL;
+    layers_t ly;
+    if (layers_init(&ly, hbm, Mb, Nb, Z)) {
+        layers_free(&ly);
+        return ORC_ENOMEM;
+    }
+    long N = ly.N;
+    int16_t *L = malloc(sizeof(int16_t) * (size_t)N);
+    int8_t *R = malloc((size_t)ly.E);
+    int32_t *Q = malloc(sizeof(int32_t) * (size_t)Nb);
+    long *nv = malloc(sizeof(long) * (size_t)Nb);
+    uint8_t *x = malloc((size_t)N);
+    if (!L || !R || !Q || !nv || !x) {
+        free(L); free(R); free(Q); free(nv); free(x); layers_free(&ly);
+        return ORC_ENOMEM;
+    }
+    for (int64_t f = 0; f < F; f++) {
+        const int8_t *Z0 = llr + f * N;
+        for (long n = 0; n < N; n++)
+            L[n] = Z0[n];
+        memset(R, 0, (size_t)ly.E);
+        int done = 0, k;
+        for (k = 1; k <= max_iter && !done; k++) {
+            for (int i = 0; i < Mb; i++) {
+                int d = ly.deg[i];
+                for (int r = 0; r < Z; r++) {
+                    for (int e = 0; e < d; e++) {
+                        nv[e] = var_of(ly.col[i * Nb + e], ly.shift[i * Nb + e], r, Z);
+                        Q[e] = sat16((int32_t)L[nv[e]] - R[edge_of(&ly, i, r, e)]);
+                    }
+                    for (int e = 0; e < d; e++) {
+                        int32_t m = INT32_MAX;
+                        int neg = 0;
+                        for (int e2 = 0; e2 < d; e2++) {
+                            if (e2 == e)
+                                continue;
+                            int32_t a = Q[e2] < 0 ? -Q[e2] : Q[e2];
+                            if (a > 127)
+                                a = 127;
+                            if (a < m)
+                                m = a;
+                            if (Q[e2] < 0)
+                                neg ^= 1;
+                        }
+                        int32_t mag;
+                        if (wq > 0) {
+                            mag = (wq * m + 8) >> 4;
+                            if (mag > 127)
+                                mag = 127;
+                        } else {
+                            mag = m - offset;
+                            if (mag < 0)
+                                mag = 0;
+                        }
+                        R[edge_of(&ly, i, r, e)] = (int8_t)(neg ? -mag : mag);
+                    }
+                }
+            }
+            for (long n = 0; n < N; n++)
+                L[n] = Z0[n];
+            for (int i = 0; i < Mb; i++)
+                for (int r = 0; r < Z; r++)
+                    for (int e = 0; e < ly.deg[i]; e++) {
+                        long n = var_of(ly.col[i * Nb + e], ly.shift[i * Nb + e], r, Z);
+                        L[n] = (int16_t)sat16((int32_t)L[n] + R[edge_of(&ly, i, r, e)]);
+                    }
+            for (long n = 0; n < N; n++)
+                x[n] = L[n] > 0 ? 0 : 1;
+            if (early_term && syndrome_zero(hbm, Mb, Nb, Z, x))
+                done = 1;
+        }
+        uint8_t good = done ? 1 : (uint8_t)syndrome_zero(hbm, Mb, Nb, Z, x);
+        if (bits)
+            memcpy(bits + f * N, x, (size_t)N);
+        if (post)
+            memcpy(post + f * N, L, sizeof(int16_t) * (size_t)N);
+        if (iters)
+            iters[f] = k - 1;
+        if (ok)
+            ok[f] = good;
+    }
+    free(L); free(R); free(Q); free(nv); free(x); layers_free(&ly);
+    return ORC_OK;
+}
+
 /* int8 quantiser of channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rint rounding half to even (the default rounding mode). */
 int orc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale)
