@@ -117,6 +117,24 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
                    int32_t *iters, uint8_t *ok, void *stream);
 
 /*
+ * Flooding (two-phase) min-sum, for comparison with the layered schedule
+ * (Sec. 4, eqs. 18-23 without layering). Each iteration first computes every
+ * check row's new messages from the posteriors of the previous iteration
+ * (eqs. 22-23), then sets every posterior to the channel value plus the new
+ * messages at that position, added in ascending block-row order (eq. 20),
+ * then tests H x = 0 (eq. 21). Arguments, layouts, arithmetic (FP32 with
+ * alpha; int8 with offset or wq/16, saturating) and outputs as
+ * ldpc_decode_f32 / ldpc_decode_i8 without weight tables. Needs run-time
+ * specialisation (LDPC_ERANGE if LDPC_JIT=0).
+ */
+int ldpc_decode_flood_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                          float alpha, int early_term, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok,
+                          void *stream);
+int ldpc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                         int offset, int wq, int early_term, uint8_t *bits, int16_t *post, int32_t *iters,
+                         uint8_t *ok, void *stream);
+
+/*
  * Decode-layout autotuner. Times the code-specialised decode kernel of
  * `path` (0 FP32, 1 int8) over candidate layouts -- frame groups per
  * workgroup, frames per thread, and how many block rows keep their gather

@@ -24,7 +24,7 @@ GPU = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-pack
 
 
 JIT_SOURCES = [("jit_decode.hip", "kJitDecodeSource"), ("jit_nms.hip", "kJitNmsSource"),
-               ("jit_batch.hip", "kJitBatchSource")]
+               ("jit_batch.hip", "kJitBatchSource"), ("jit_flood.hip", "kJitFloodSource")]
 
 
 def _embed_jit_source():

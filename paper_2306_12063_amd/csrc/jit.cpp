@@ -25,6 +25,7 @@ namespace ldpc {
 extern const char kJitDecodeSource[];
 extern const char kJitNmsSource[];
 extern const char kJitBatchSource[];
+extern const char kJitFloodSource[];
 
 namespace {
 
@@ -248,6 +249,46 @@ static int get_decode_function(const Sched &sc, const DecodeLaunch &lc, int path
     const std::string name = decode_kernel_name(sc, path);
     return get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n",
                         name.c_str(), fn);
+}
+
+DecodeLaunch flood_launch(const Sched &sc)
+{
+    // the flooding kernel keeps two FP32 arrays (posteriors, channel values)
+    // in LDS; the widest workgroup of <= 256 threads with the most busy lanes
+    DecodeLaunch best{};
+    double best_util = -1.0;
+    for (int G = 1; G * sc.Z <= kMaxThreads && G <= 64; ++G) {
+        const int FWp = G | 1;
+        const size_t lds = 2 * (size_t)(sc.N + sc.Z) * FWp * sizeof(float);
+        if (lds > (size_t)kLdsBudget)
+            break;
+        const int threads = ((G * sc.Z + 63) / 64) * 64;
+        const double util = (double)(G * sc.Z) / threads;
+        if (util > best_util + 1e-9 || (util > best_util - 1e-9 && G > best.G)) {
+            best_util = util;
+            best = DecodeLaunch{G, 1, G, FWp, threads, lds, 0};
+        }
+    }
+    const int per_row = sc.E / sc.Z;
+    best.hoist = 2 * per_row <= 176 ? sc.Mb : 0;
+    return best;
+}
+
+int launch_jit_flood(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr, int64_t F,
+                     int max_iter, float alpha, int offset, int wq, int et, uint8_t *bits, void *post, int32_t *iters,
+                     uint8_t *ok, hipStream_t stream)
+{
+    const std::string name = std::string("ldpc_flood_") + (path == 0 ? "f32" : "i8") + "_z" + std::to_string(sc.Z) +
+                             "_mb" + std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb);
+    hipFunction_t fn;
+    int rc = get_function("flood", kJitFloodSource, prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n",
+                          name.c_str(), &fn);
+    if (rc)
+        return rc;
+    long long Fll = (long long)F;
+    void *args[] = {(void *)&llr, (void *)&Fll, (void *)&max_iter, (void *)&alpha, (void *)&offset, (void *)&wq,
+                    (void *)&et, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
+    return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "flood decode");
 }
 
 DecodeLaunch jit_default_launch(const Sched &sc, int path)

@@ -299,6 +299,57 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
                          "ldpc_decode_i8");
 }
 
+static int flood_common(const int16_t *hbm, int Mb, int Nb, int Z, const void *llr, int64_t F, int max_iter,
+                        const void *bits, const int32_t *iters, Sched *sc, DecodeLaunch *lc)
+{
+    clear_error();
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(*sc, F, max_iter)))
+        return rc;
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the flooding decoder needs run-time specialisation (LDPC_JIT=0 is set)");
+    *lc = flood_launch(*sc);
+    if (lc->G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the flooding decoder's LDS budget", sc->N);
+    return LDPC_OK;
+}
+
+int ldpc_decode_flood_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                          float alpha, int early_term, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok,
+                          void *stream)
+{
+    Sched sc;
+    DecodeLaunch lc{};
+    int rc = flood_common(hbm, Mb, Nb, Z, llr, F, max_iter, bits, iters, &sc, &lc);
+    if (rc || F == 0)
+        return rc;
+    return launch_jit_flood(sc, lc, 0, 0, llr, F, max_iter, alpha, 0, 0, early_term, bits, post, iters, ok,
+                            (hipStream_t)stream);
+}
+
+int ldpc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                         int offset, int wq, int early_term, uint8_t *bits, int16_t *post, int32_t *iters,
+                         uint8_t *ok, void *stream)
+{
+    if (offset < 0 || offset > 127)
+        return fail(LDPC_EINVAL, "offset must be in [0, 127] (got %d)", offset);
+    if (wq < 0 || wq > 31)
+        return fail(LDPC_EINVAL, "wq must be in [0, 31] (got %d)", wq);
+    Sched sc;
+    DecodeLaunch lc{};
+    int rc = flood_common(hbm, Mb, Nb, Z, llr, F, max_iter, bits, iters, &sc, &lc);
+    if (rc || F == 0)
+        return rc;
+    return launch_jit_flood(sc, lc, 1, wq > 0 ? 1 : 0, llr, F, max_iter, 0.0f, offset, wq, early_term, bits, post,
+                            iters, ok, (hipStream_t)stream);
+}
+
 int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
                          int32_t out[5], float *ms, void *stream)
 {

@@ -88,6 +88,11 @@ DecodeLaunch jit_default_launch(const Sched &sc, int path);
 // Bytes of per-lane scratch the specialised decode kernel for this layout
 // needs (register spills); compiles the variant if necessary.
 int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes);
+// Flooding schedule (jit_flood.hip): layout and launch.
+DecodeLaunch flood_launch(const Sched &sc);
+int launch_jit_flood(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr, int64_t F,
+                     int max_iter, float alpha, int offset, int wq, int et, uint8_t *bits, void *post, int32_t *iters,
+                     uint8_t *ok, hipStream_t stream);
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
