@@ -53,6 +53,8 @@ def lib():
                 "orc_decode_flood_f64": [p, i32, i32, i32, p, i64, i32, f64, i32, p, p, p, p],
                 "orc_decode_flood_i8": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
                 "orc_quantize_i8": [p, p, i64, f32],
+                "orc_decode_q16": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
+                "orc_quantize_q16": [p, p, i64, f32, i32],
                 "orc_nms_train": [p, i32, i32, i32, p, p, i64, i32, p, i32, p, p, p],
                 "orc_frame_bits": [u64, i64, i64, p],
                 "orc_frame_noise": [u64, i64, i64, p],
@@ -215,6 +217,34 @@ def decode_flood_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, early_term=True):
                                      int(bool(early_term)), _ptr(bits), _ptr(post), _ptr(iters), _ptr(ok)),
            "decode_flood_i8")
     return bits, post, iters, ok
+
+
+def decode_q16(hbm, Z, llr, max_iter=10, wq=12, wrap=True, early_term=True):
+    """The paper's fixed point (Sec. 5): layered min-sum on int16 values with
+    wrap-around (wrap=True) or symmetric saturating arithmetic, normalisation
+    wq/16. llr: int16 [F][N] (Q_B-bit values). Returns (bits, posteriors i16,
+    iterations, ok)."""
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    llr = np.ascontiguousarray(llr, dtype=np.int16)
+    F, N = llr.shape
+    if N != Nb * Z:
+        raise ValueError("llr has the wrong length")
+    bits = np.zeros((F, N), np.uint8)
+    post = np.zeros((F, N), np.int16)
+    iters = np.zeros(F, np.int32)
+    ok = np.zeros(F, np.uint8)
+    _check(lib().orc_decode_q16(_ptr(h), Mb, Nb, Z, _ptr(llr), F, max_iter, wq, int(bool(wrap)),
+                                int(bool(early_term)), _ptr(bits), _ptr(post), _ptr(iters), _ptr(ok)), "decode_q16")
+    return bits, post, iters, ok
+
+
+def quantize_q16(llr, scale=16.0, qmax=1023):
+    """Q_B-bit quantiser (Q_B = 10: qmax = 1023): clamp(rint(scale * llr), +-qmax)."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    q = np.zeros(llr.shape, np.int16)
+    _check(lib().orc_quantize_q16(_ptr(llr), _ptr(q), llr.size, scale, qmax), "quantize_q16")
+    return q
 
 
 def quantize_i8(llr, scale=4.0):

@@ -507,6 +507,122 @@ int orc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t 
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The paper's own fixed point (Sec. 5): Q_B-bit LLRs in int16              */
+/* ------------------------------------------------------------------------ */
+
+/* two's-complement wrap to int16, as storing an int into int16_t does */
+static int32_t wrap16(int32_t x)
+{
+    return (int32_t)(int16_t)(uint16_t)(uint32_t)x;
+}
+
+static int32_t q16_fix(int32_t x, int wrap)
+{
+    return wrap ? wrap16(x) : sat16(x);
+}
+
+/*
+ * Layered min-sum on int16 values (Sec. 5: Q_B-bit LLRs held in int16 with
+ * headroom, C's wrap-around arithmetic; wrap = 0 gives the saturating twin
+ * with symmetric saturation at +-32767). Per check row, with F the wrap or
+ * the saturation:
+ *   Q_e = F(L[n_e] - R_e);  a_e = |Q_e| (exact, up to 32768)
+ *   m_e = min_{e' != e} a_e';  R_e = F(s_e * ((wq * m_e + 8) >> 4))
+ *   L[n_e] = F(Q_e + R_e)
+ * wq/16 is the normalisation (16: plain min-sum). Messages are 16-bit, with
+ * no clipping below 16 bits. Hard decision and syndrome as the other decoders.
+ */
+int orc_decode_q16(const int16_t *hbm, int Mb, int Nb, int Z, const int16_t *llr, int64_t F, int max_iter, int wq,
+                   int wrap, int early_term, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok)
+{
+    if (check_base(hbm, Mb, Nb, Z, 1) || F < 0 || max_iter < 1 || wq < 1 || wq > 31 || (F > 0 && !llr))
+        return ORC_EINVAL;
+    layers_t ly;
+    if (layers_init(&ly, hbm, Mb, Nb, Z)) {
+        layers_free(&ly);
+        return ORC_ENOMEM;
+    }
+    long N = ly.N;
+    int16_t *L = malloc(sizeof(int16_t) * (size_t)N);
+    int16_t *R = malloc(sizeof(int16_t) * (size_t)ly.E);
+    int32_t *Q = malloc(sizeof(int32_t) * (size_t)Nb);
+    int32_t *Rn = malloc(sizeof(int32_t) * (size_t)Nb);
+    long *nv = malloc(sizeof(long) * (size_t)Nb);
+    uint8_t *x = malloc((size_t)N);
+    if (!L || !R || !Q || !Rn || !nv || !x) {
+        free(L); free(R); free(Q); free(Rn); free(nv); free(x); layers_free(&ly);
+        return ORC_ENOMEM;
+    }
+    for (int64_t f = 0; f < F; f++) {
+        for (long n = 0; n < N; n++)
+            L[n] = llr[f * N + n];
+        memset(R, 0, sizeof(int16_t) * (size_t)ly.E);
+        int done = 0, k;
+        for (k = 1; k <= max_iter && !done; k++) {
+            for (int i = 0; i < Mb; i++) {
+                int d = ly.deg[i];
+                for (int r = 0; r < Z; r++) {
+                    for (int e = 0; e < d; e++) {
+                        nv[e] = var_of(ly.col[i * Nb + e], ly.shift[i * Nb + e], r, Z);
+                        Q[e] = q16_fix((int32_t)L[nv[e]] - R[edge_of(&ly, i, r, e)], wrap);
+                    }
+                    for (int e = 0; e < d; e++) {
+                        int32_t m = INT32_MAX;
+                        int neg = 0;
+                        for (int e2 = 0; e2 < d; e2++) {
+                            if (e2 == e)
+                                continue;
+                            int32_t a = Q[e2] < 0 ? -Q[e2] : Q[e2];
+                            if (a < m)
+                                m = a;
+                            if (Q[e2] < 0)
+                                neg ^= 1;
+                        }
+                        int32_t mag = (wq * m + 8) >> 4;
+                        Rn[e] = q16_fix(neg ? -mag : mag, wrap);
+                    }
+                    for (int e = 0; e < d; e++) {
+                        R[edge_of(&ly, i, r, e)] = (int16_t)Rn[e];
+                        L[nv[e]] = (int16_t)q16_fix(Q[e] + Rn[e], wrap);
+                    }
+                }
+            }
+            for (long n = 0; n < N; n++)
+                x[n] = L[n] > 0 ? 0 : 1;
+            if (early_term && syndrome_zero(hbm, Mb, Nb, Z, x))
+                done = 1;
+        }
+        uint8_t good = done ? 1 : (uint8_t)syndrome_zero(hbm, Mb, Nb, Z, x);
+        if (bits)
+            memcpy(bits + f * N, x, (size_t)N);
+        if (post)
+            memcpy(post + f * N, L, sizeof(int16_t) * (size_t)N);
+        if (iters)
+            iters[f] = k - 1;
+        if (ok)
+            ok[f] = good;
+    }
+    free(L); free(R); free(Q); free(Rn); free(nv); free(x); layers_free(&ly);
+    return ORC_OK;
+}
+
+/* Q_B-bit quantiser: q = clamp(rint(scale * llr), -qmax, qmax), half to even. */
+int orc_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax)
+{
+    if (n < 0 || qmax < 1 || qmax > 32767)
+        return ORC_EINVAL;
+    for (int64_t k = 0; k < n; k++) {
+        float v = rintf(scale * llr[k]);
+        if (v > (float)qmax)
+            v = (float)qmax;
+        if (v < (float)-qmax)
+            v = (float)-qmax;
+        q[k] = (int16_t)v;
+    }
+    return ORC_OK;
+}
+
 /* int8 quantiser of channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rint rounding half to even (the default rounding mode). */
 int orc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale)
