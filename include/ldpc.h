@@ -277,6 +277,24 @@ int ldpc_codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, co
                           int32_t out[2], float *ms, void *stream);
 
 /*
+ * The paper's own fixed point (Sec. 5): layered min-sum on int16 values,
+ * Q_B-bit LLRs with headroom. Per check row: Q = fix(L - R), the two
+ * smallest |Q| and the sign parity in one scan, message R =
+ * fix(sgn * ((wq * m + 8) >> 4)) with m the minimum over the other edges,
+ * L = fix(Q + R); fix() wraps around to int16 (wrap != 0, the C decoder's
+ * arithmetic) or saturates symmetrically at +-32767 (wrap == 0). wq/16 is
+ * the normalisation, wq in [1, 31] (16: plain min-sum). llr: device i16
+ * [F][N] (see ldpc_quantize_q16); post: nullable device i16 [F][N]; other
+ * arguments as ldpc_decode_i8. Needs run-time specialisation.
+ *
+ * ldpc_quantize_q16: q = clamp(rint(scale * llr), -qmax, qmax), half to
+ * even (Q_B = 10: qmax = 1023). llr: device f32 [n], q: device i16 [n].
+ */
+int ldpc_decode_q16(const int16_t *hbm, int Mb, int Nb, int Z, const int16_t *llr, int64_t F, int max_iter, int wq,
+                    int wrap, int early_term, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, void *stream);
+int ldpc_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax, void *stream);
+
+/*
  * int8 quantiser for channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rounding half to even. llr: device f32 [n], q: device i8 [n].
  */

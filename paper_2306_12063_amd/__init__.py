@@ -19,7 +19,7 @@ __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
     "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset",
-    "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -55,6 +55,8 @@ EXPORTS = {
     "ldpc_codeset_autotune": ([_p, _i32, _p, _p, _p, _i64, _i32, _p, _p, _p, C.c_size_t, _p, _p, _p], _i32),
     "ldpc_decode_flood_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_flood_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
+    "ldpc_decode_q16": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
+    "ldpc_quantize_q16": ([_p, _p, _i64, _f32, _i32, _p], _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -246,6 +248,37 @@ def ldpc_decode_flood_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, early_term=Tr
                                       _dev(bits, torch.uint8, "bits", (F, N)), _opt(post, torch.int16, "post", (F, N)),
                                       _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)),
                                       _stream(stream)), "ldpc_decode_flood_i8")
+    return bits, post, iters, ok
+
+
+def ldpc_quantize_q16(llr, scale=16.0, qmax=1023, out=None, stream=None):
+    """Q_B-bit LLRs in int16 (Q_B = 10: qmax = 1023): clamp(rint(scale * llr), +-qmax)."""
+    torch = _torch()
+    out = torch.empty(llr.shape, dtype=torch.int16, device=llr.device) if out is None else out
+    _check(lib().ldpc_quantize_q16(_dev(llr, torch.float32, "llr"), _dev(out, torch.int16, "out", tuple(llr.shape)),
+                                   llr.numel(), float(scale), int(qmax), _stream(stream)), "ldpc_quantize_q16")
+    return out
+
+
+def ldpc_decode_q16(hbm, Z, llr, max_iter=10, wq=12, wrap=True, early_term=True, bits=None, post=None, iters=None,
+                    ok=None, want_post=True, stream=None):
+    """The paper's int16 fixed point (wrap-around, or saturating with wrap=False).
+    Returns (bits, post i16 or None, iters, ok)."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    dev = llr.device
+    bits = torch.empty((F, N), dtype=torch.uint8, device=dev) if bits is None else bits
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.int16, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+    ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+    _check(lib().ldpc_decode_q16(_hptr(h), Mb, Nb, Z, _dev(llr, torch.int16, "llr", (F, Nb * Z)), F, int(max_iter),
+                                 int(wq), int(bool(wrap)), int(bool(early_term)),
+                                 _dev(bits, torch.uint8, "bits", (F, N)), _opt(post, torch.int16, "post", (F, N)),
+                                 _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)),
+                                 _stream(stream)), "ldpc_decode_q16")
     return bits, post, iters, ok
 
 

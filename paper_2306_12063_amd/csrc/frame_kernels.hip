@@ -90,6 +90,18 @@ __global__ void k_quantize_i8(const float *__restrict__ in, int8_t *__restrict__
     out[i] = (int8_t)v;
 }
 
+// Q_B-bit quantiser of the paper's fixed point: clamp(rint(scale x), +-qmax).
+__global__ void k_quantize_q16(const float *__restrict__ in, int16_t *__restrict__ out, int64_t n, float scale,
+                               float qmax)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float v = rintf(scale * in[i]);
+    v = fminf(fmaxf(v, -qmax), qmax);
+    out[i] = (int16_t)v;
+}
+
 // Direct encoder. A workgroup encodes G frames; thread (g, r) owns row r of
 // every Z-bit block of frame g.
 //   S_i[r] = xor_j u_j[(r + H(i,j)) mod Z] over the information columns (eq. 15)
@@ -239,6 +251,12 @@ inline int grid_for(int64_t work, int threads) { return (int)((work + threads - 
 int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_quantize_i8, dim3(grid_for(n, 256)), dim3(256), 0, stream, llr, q, n, scale);
+    return check_launch(__func__);
+}
+
+int launch_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_quantize_q16, dim3(grid_for(n, 256)), dim3(256), 0, stream, llr, q, n, scale, (float)qmax);
     return check_launch(__func__);
 }
 

@@ -26,6 +26,7 @@ extern const char kJitDecodeSource[];
 extern const char kJitNmsSource[];
 extern const char kJitBatchSource[];
 extern const char kJitFloodSource[];
+extern const char kJitQ16Source[];
 
 namespace {
 
@@ -289,6 +290,24 @@ int launch_jit_flood(const Sched &sc, const DecodeLaunch &lc, int path, int mode
     void *args[] = {(void *)&llr, (void *)&Fll, (void *)&max_iter, (void *)&alpha, (void *)&offset, (void *)&wq,
                     (void *)&et, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
     return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "flood decode");
+}
+
+int launch_jit_q16(const Sched &sc, const DecodeLaunch &lc, int wrap, const int16_t *llr, int64_t F, int max_iter,
+                   int wq, int et, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, hipStream_t stream)
+{
+    const std::string name = std::string("ldpc_q16_") + (wrap ? "wrap" : "sat") + "_z" + std::to_string(sc.Z) +
+                             "_mb" + std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb);
+    hipFunction_t fn;
+    int rc = get_function("q16", kJitQ16Source,
+                          prelude(sc, lc, 1, 0) + "#define LDPC_WRAP " + std::to_string(wrap ? 1 : 0) +
+                              "\n#define LDPC_KERNEL " + name + "\n",
+                          name.c_str(), &fn);
+    if (rc)
+        return rc;
+    long long Fll = (long long)F;
+    void *args[] = {(void *)&llr, (void *)&Fll, (void *)&max_iter, (void *)&wq, (void *)&et, (void *)&bits,
+                    (void *)&post, (void *)&iters, (void *)&ok};
+    return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "q16 decode");
 }
 
 DecodeLaunch jit_default_launch(const Sched &sc, int path)

@@ -521,6 +521,43 @@ int ldpc_fallback_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *ll
                     (hipStream_t)stream);
 }
 
+int ldpc_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax, void *stream)
+{
+    clear_error();
+    if (n < 0 || qmax < 1 || qmax > 32767)
+        return fail(LDPC_EINVAL, "negative size or qmax outside [1, 32767]");
+    if (n == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, q}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_quantize_q16(llr, q, n, scale, qmax, (hipStream_t)stream), "ldpc_quantize_q16");
+}
+
+int ldpc_decode_q16(const int16_t *hbm, int Mb, int Nb, int Z, const int16_t *llr, int64_t F, int max_iter, int wq,
+                    int wrap, int early_term, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (wq < 1 || wq > 31)
+        return fail(LDPC_EINVAL, "wq must be in [1, 31] (got %d)", wq);
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "the int16 decoder needs run-time specialisation (LDPC_JIT=0 is set)");
+    DecodeLaunch lc = jit_default_launch(sc, 0);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    return launch_jit_q16(sc, lc, wrap ? 1 : 0, llr, F, max_iter, wq, early_term, bits, post, iters, ok,
+                          (hipStream_t)stream);
+}
+
 int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *stream)
 {
     clear_error();

@@ -66,6 +66,7 @@ int launch_decode_i8(const Sched &sc, const DecodeLaunch &lc, const int8_t *llr,
                      int max_iter, int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits,
                      int16_t *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
 int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream);
+int launch_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax, hipStream_t stream);
 int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
 int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream);
 int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
@@ -93,6 +94,9 @@ DecodeLaunch flood_launch(const Sched &sc);
 int launch_jit_flood(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr, int64_t F,
                      int max_iter, float alpha, int offset, int wq, int et, uint8_t *bits, void *post, int32_t *iters,
                      uint8_t *ok, hipStream_t stream);
+// The paper's int16 Q_B-bit fixed point (jit_q16.hip).
+int launch_jit_q16(const Sched &sc, const DecodeLaunch &lc, int wrap, const int16_t *llr, int64_t F, int max_iter,
+                   int wq, int et, uint8_t *bits, int16_t *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
