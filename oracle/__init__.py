@@ -55,6 +55,8 @@ def lib():
                 "orc_quantize_i8": [p, p, i64, f32],
                 "orc_decode_q16": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
                 "orc_quantize_q16": [p, p, i64, f32, i32],
+                "orc_shift_packed": [p, p, i64, i32, i32],
+                "orc_encode_packed": [p, i32, i32, i32, p, p, i64],
                 "orc_nms_train": [p, i32, i32, i32, p, p, i64, i32, p, i32, p, p, p],
                 "orc_frame_bits": [u64, i64, i64, p],
                 "orc_frame_noise": [u64, i64, i64, p],
@@ -245,6 +247,26 @@ def quantize_q16(llr, scale=16.0, qmax=1023):
     q = np.zeros(llr.shape, np.int16)
     _check(lib().orc_quantize_q16(_ptr(llr), _ptr(q), llr.size, scale, qmax), "quantize_q16")
     return q
+
+
+def shift_packed(blocks, Z, s):
+    """Cyclic shift of packed Z-bit blocks (LSB-first bytes, [F][ceil(Z/8)]):
+    out[r] = in[(r + s) mod Z]."""
+    blocks = np.ascontiguousarray(blocks, dtype=np.uint8)
+    out = np.zeros_like(blocks)
+    _check(lib().orc_shift_packed(_ptr(blocks), _ptr(out), blocks.shape[0], Z, s), "shift_packed")
+    return out
+
+
+def encode_packed(hbm, Z, info_packed):
+    """Direct encoder on packed bits (LSB-first): info [F][ceil(K/8)] -> cw [F][ceil(N/8)]."""
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    info_packed = np.ascontiguousarray(info_packed, dtype=np.uint8)
+    F = info_packed.shape[0]
+    cw = np.zeros((F, (Nb * Z + 7) // 8), np.uint8)
+    _check(lib().orc_encode_packed(_ptr(h), Mb, Nb, Z, _ptr(info_packed), _ptr(cw), F), "encode_packed")
+    return cw
 
 
 def quantize_i8(llr, scale=4.0):

@@ -623,6 +623,72 @@ int orc_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int q
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Packed bits (Sec. 3, bitmap encoder): bit k of a frame is bit (k mod 8)  */
+/* of byte k/8 (least significant bit first); a frame of n bits takes       */
+/* ceil(n/8) bytes, unused high bits of its last byte are 0.                */
+/* ------------------------------------------------------------------------ */
+
+static void unpack_bits(const uint8_t *in, long n, uint8_t *out)
+{
+    for (long k = 0; k < n; k++)
+        out[k] = (uint8_t)((in[k >> 3] >> (k & 7)) & 1u);
+}
+
+static void pack_bits(const uint8_t *in, long n, uint8_t *out)
+{
+    memset(out, 0, (size_t)((n + 7) / 8));
+    for (long k = 0; k < n; k++)
+        out[k >> 3] |= (uint8_t)((in[k] & 1u) << (k & 7));
+}
+
+/* Cyclic shift of F packed Z-bit blocks by s (0 <= s < Z), the operation
+ * the direct encoder applies to every block (eqs. 12-15):
+ * out[r] = in[(r + s) mod Z]. */
+int orc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s)
+{
+    if (F < 0 || Z < 1 || s < 0 || s >= Z)
+        return ORC_EINVAL;
+    long nb = (Z + 7) / 8;
+    uint8_t *a = malloc((size_t)Z), *b = malloc((size_t)Z);
+    if (!a || !b) {
+        free(a); free(b);
+        return ORC_ENOMEM;
+    }
+    for (int64_t f = 0; f < F; f++) {
+        unpack_bits(in + f * nb, Z, a);
+        for (int r = 0; r < Z; r++)
+            b[r] = a[(r + s) % Z];
+        pack_bits(b, Z, out + f * nb);
+    }
+    free(a); free(b);
+    return ORC_OK;
+}
+
+/* Packed direct encoder: the codeword of orc_encode for the unpacked
+ * information bits, packed. info: [F][ceil(K/8)], cw: [F][ceil(N/8)]. */
+int orc_encode_packed(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, uint8_t *cw, int64_t F)
+{
+    if (check_base(hbm, Mb, Nb, Z, 0) || F < 0)
+        return ORC_EINVAL;
+    long K = (long)(Nb - Mb) * Z, N = (long)Nb * Z;
+    long kb = (K + 7) / 8, nbyt = (N + 7) / 8;
+    uint8_t *u = malloc((size_t)K), *c = malloc((size_t)N);
+    if (!u || !c) {
+        free(u); free(c);
+        return ORC_ENOMEM;
+    }
+    int rc = ORC_OK;
+    for (int64_t f = 0; f < F && rc == ORC_OK; f++) {
+        unpack_bits(info + f * kb, K, u);
+        rc = orc_encode(hbm, Mb, Nb, Z, u, c, 1);
+        if (rc == ORC_OK)
+            pack_bits(c, N, cw + f * nbyt);
+    }
+    free(u); free(c);
+    return rc;
+}
+
 /* int8 quantiser of channel LLRs: q = clamp(rint(scale * llr), -127, 127),
  * rint rounding half to even (the default rounding mode). */
 int orc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale)
