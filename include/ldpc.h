@@ -135,6 +135,23 @@ int ldpc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t
                          uint8_t *ok, void *stream);
 
 /*
+ * Packed bits (the bitmap encoder of Sec. 3). A frame of n bits takes
+ * ceil(n/8) bytes; bit k is bit (k mod 8) of byte k/8 (least significant
+ * bit first); unused high bits of the last byte are written as 0 and
+ * ignored on input.
+ *
+ * ldpc_encode_packed: the direct encoder (eqs. 8-15) on packed bits, any Z:
+ *   info : device u8 [F][ceil(K/8)],  cw : device u8 [F][ceil(N/8)].
+ *   Same structure requirements and errors as ldpc_encode.
+ * ldpc_shift_packed: the cyclic shift the encoder applies to Z-bit blocks,
+ *   out[r] = in[(r + s) mod Z] for each of F blocks of ceil(Z/8) bytes
+ *   (Algorithm A1 generalised to any Z), 0 <= s < Z.
+ */
+int ldpc_encode_packed(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, uint8_t *cw, int64_t F,
+                       void *stream);
+int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, void *stream);
+
+/*
  * Decode-layout autotuner. Times the code-specialised decode kernel of
  * `path` (0 FP32, 1 int8) over candidate layouts -- frame groups per
  * workgroup, frames per thread, and how many block rows keep their gather

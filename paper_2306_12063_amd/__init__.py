@@ -19,7 +19,8 @@ __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
     "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset",
-    "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16",
+    "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -57,6 +58,8 @@ EXPORTS = {
     "ldpc_decode_flood_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_q16": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_quantize_q16": ([_p, _p, _i64, _f32, _i32, _p], _i32),
+    "ldpc_encode_packed": ([_p, _i32, _i32, _i32, _p, _p, _i64, _p], _i32),
+    "ldpc_shift_packed": ([_p, _p, _i64, _i32, _i32, _p], _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -249,6 +252,32 @@ def ldpc_decode_flood_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, early_term=Tr
                                       _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)),
                                       _stream(stream)), "ldpc_decode_flood_i8")
     return bits, post, iters, ok
+
+
+def ldpc_encode_packed(hbm, Z, info, out=None, stream=None):
+    """Direct encoder on packed bits (LSB-first bytes): info u8 [F][ceil(K/8)]
+    -> codewords u8 [F][ceil(N/8)]."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F = info.shape[0]
+    N, K = Nb * Z, (Nb - Mb) * Z
+    out = torch.empty((F, (N + 7) // 8), dtype=torch.uint8, device=info.device) if out is None else out
+    _check(lib().ldpc_encode_packed(_hptr(h), Mb, Nb, Z, _dev(info, torch.uint8, "info", (F, (K + 7) // 8)),
+                                    _dev(out, torch.uint8, "out", (F, (N + 7) // 8)), F, _stream(stream)),
+           "ldpc_encode_packed")
+    return out
+
+
+def ldpc_shift_packed(blocks, Z, s, out=None, stream=None):
+    """Cyclic shift of packed Z-bit blocks u8 [F][ceil(Z/8)]: out[r] = in[(r + s) mod Z]."""
+    torch = _torch()
+    F = blocks.shape[0]
+    out = torch.empty_like(blocks) if out is None else out
+    _check(lib().ldpc_shift_packed(_dev(blocks, torch.uint8, "blocks", (F, (Z + 7) // 8)),
+                                   _dev(out, torch.uint8, "out", (F, (Z + 7) // 8)), F, int(Z), int(s),
+                                   _stream(stream)), "ldpc_shift_packed")
+    return out
 
 
 def ldpc_quantize_q16(llr, scale=16.0, qmax=1023, out=None, stream=None):

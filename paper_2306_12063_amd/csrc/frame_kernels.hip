@@ -301,4 +301,189 @@ int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, 
     return check_launch(__func__);
 }
 
+// ---------------------------------------------------------------------------
+// Packed bits (bitmap encoder of Sec. 3). Bit k of a frame is bit k mod 8 of
+// byte k/8; in LDS a frame's bits are 32-bit words, bit k at bit k mod 32 of
+// word k/32. A thread produces one 32-bit word of a Z-bit block: its bits
+// r = 32w .. 32w + nv - 1 come from source bits (r + s) mod Z, i.e. from at
+// most two runs of the source block (one wrap), each read at an arbitrary
+// bit position with a funnel shift. This generalises the word rotation of
+// Algorithm A1 (which needs Z to be a multiple of the word size) to any Z.
+// ---------------------------------------------------------------------------
+
+// 32 bits of the word stream W starting at bit position p (W must hold one
+// more word than the highest word read)
+__device__ __forceinline__ uint32_t bits32(const uint32_t *W, int p)
+{
+    const int q = p >> 5;
+    return __builtin_amdgcn_alignbit(W[q + 1], W[q], (uint32_t)(p & 31));
+}
+
+__device__ __forceinline__ uint32_t low_mask(int n) { return n >= 32 ? 0xffffffffu : ((1u << n) - 1u); }
+
+// word w (nv valid bits) of the block at bit offset b0 of W, cyclically
+// shifted by s: bit t = source bit (32w + t + s) mod Z
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t *W, int b0, int Z, int s, int w, int nv)
+{
+    int o = 32 * w + s;
+    o = o >= Z ? o - Z : o;
+    o = o >= Z ? o - Z : o;   // 32w < Z and s < Z
+    const int L1 = nv < Z - o ? nv : Z - o;
+    uint32_t x = bits32(W, b0 + o) & low_mask(L1);
+    if (L1 < nv)
+        x |= bits32(W, b0) << L1;
+    return x & low_mask(nv);
+}
+
+// stage packed frames (nbytes each) into LDS words (nw words each, zeroed
+// beyond the data) for frames f0 .. f0+G-1
+__device__ __forceinline__ void stage_bytes(const uint8_t *__restrict__ src, int64_t nbytes, int nw, int G, int64_t f0,
+                                            int64_t F, uint32_t *W)
+{
+    for (int k = threadIdx.x; k < G * nw; k += blockDim.x)
+        W[k] = 0u;
+    __syncthreads();
+    uint8_t *Wb = (uint8_t *)W;
+    for (int g = 0; g < G; ++g) {
+        if (f0 + g >= F)
+            break;
+        const uint8_t *p = src + (f0 + g) * nbytes;
+        for (int64_t b = threadIdx.x; b < nbytes; b += blockDim.x)
+            Wb[(size_t)g * nw * 4 + b] = p[b];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_shift_packed(const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                                               int64_t F, int Z, int s, int G)
+{
+    extern __shared__ uint32_t lw[];
+    const int ZW = (Z + 31) / 32, nw = ZW + 1;
+    const int64_t nbytes = (Z + 7) / 8;
+    const int64_t f0 = (int64_t)blockIdx.x * G;
+    uint32_t *Wi = lw, *Wo = lw + (size_t)G * nw;
+    stage_bytes(in, nbytes, nw, G, f0, F, Wi);
+    const int g = threadIdx.x / ZW, w = threadIdx.x - g * ZW;
+    if (g < G && f0 + g < F) {
+        const int nv = Z - 32 * w < 32 ? Z - 32 * w : 32;
+        Wo[g * nw + w] = shifted_word(Wi + g * nw, 0, Z, s, w, nv);
+    }
+    __syncthreads();
+    const uint8_t *Ob = (const uint8_t *)Wo;
+    for (int gg = 0; gg < G; ++gg) {
+        if (f0 + gg >= F)
+            break;
+        for (int64_t b = threadIdx.x; b < nbytes; b += blockDim.x)
+            out[(f0 + gg) * nbytes + b] = Ob[(size_t)gg * nw * 4 + b];
+    }
+}
+
+// Packed direct encoder (eqs. 12-15 on 32-bit words). Thread (g, w) owns word
+// w of every Z-bit block of frame g: S_i[w] (eq. 15) for all block rows in
+// registers, T[w] and v_0[w] through LDS (v_0 is read at shifted positions),
+// then v_1 .. v_{Mb-1} (eqs. 13-14) OR-ed into the packed codeword in LDS at
+// bit offsets K + i Z + 32 w (blocks need not be word aligned).
+__global__ __launch_bounds__(kMaxThreads) void k_encode_packed(const Sched sc, const int G,
+                                                                const uint8_t *__restrict__ info,
+                                                                uint8_t *__restrict__ cw, int64_t F)
+{
+    extern __shared__ uint32_t lw[];
+    const int Z = sc.Z, K = sc.K, N = sc.N, Mb = sc.Mb, Kb = sc.Nb - sc.Mb;
+    const int ZW = (Z + 31) / 32;
+    const int kw = (K + 31) / 32 + 1, nwo = (N + 31) / 32 + 1, zw1 = ZW + 1;
+    const int64_t kbytes = (K + 7) / 8, nbytes = (N + 7) / 8;
+    uint32_t *U = lw;                                   // [G][kw]  information bits
+    uint32_t *T = U + (size_t)G * kw;                   // [G][zw1]
+    uint32_t *V0 = T + (size_t)G * zw1;                 // [G][zw1]
+    uint32_t *C = V0 + (size_t)G * zw1;                 // [G][nwo] codeword
+    const int64_t f0 = (int64_t)blockIdx.x * G;
+    for (int k = threadIdx.x; k < G * (2 * zw1 + nwo); k += blockDim.x)
+        T[k] = 0u;
+    stage_bytes(info, kbytes, kw, G, f0, F, U);   // (its barriers also cover the zeroing)
+    const int g = threadIdx.x / ZW, w = threadIdx.x - g * ZW;
+    const bool on = g < G && f0 + g < F;
+    const int nv = on ? (Z - 32 * w < 32 ? Z - 32 * w : 32) : 0;
+    uint32_t S[kMaxMb];
+    if (on) {
+        const uint32_t *u = U + g * kw;
+        uint32_t t = 0;
+        for (int i = 0; i < Mb; ++i) {
+            uint32_t acc = 0;
+            for (int e = 0; e < sc.deg[i]; ++e) {
+                const uint32_t ew = sc.edge[i][e];
+                const int col = (int)(ew >> 16);
+                if (col >= Kb)
+                    break;   // ascending columns: the rest are parity columns
+                acc ^= shifted_word(u, col * Z, Z, (int)(ew & 0xffffu), w, nv);
+            }
+            S[i] = acc;
+            t ^= acc;
+        }
+        T[g * zw1 + w] = t;   // T = xor_i S_i
+    }
+    __syncthreads();
+    if (on) {
+        const int hy = sc.hb[sc.enc_y];
+        V0[g * zw1 + w] = shifted_word(T + g * zw1, 0, Z, hy == 0 ? 0 : Z - hy, w, nv);   // eq. 12
+    }
+    __syncthreads();
+    if (on) {
+        const uint32_t *v0 = V0 + g * zw1;
+        uint32_t *c = C + g * nwo;
+        auto put = [&](int bit, uint32_t x) {
+            const int q = bit >> 5, sh = bit & 31;
+            atomicOr(&c[q], x << sh);
+            if (sh && sh + nv > 32)
+                atomicOr(&c[q + 1], x >> (32 - sh));
+        };
+        uint32_t v = v0[w];
+        put(K + 32 * w, v);
+        const int h0 = sc.hb[0];
+        v = shifted_word(v0, 0, Z, h0, w, nv) ^ S[0];                          // eq. 13
+        put(K + Z + 32 * w, v);
+        for (int i = 1; i <= Mb - 2; ++i) {
+            const int hi = sc.hb[i];
+            v ^= S[i] ^ (hi >= 0 ? shifted_word(v0, 0, Z, hi, w, nv) : 0u);   // eq. 14
+            put(K + (i + 1) * Z + 32 * w, v);
+        }
+        // systematic part: the information words (the last one masked to K bits)
+        for (int q = w; q < (K + 31) / 32; q += ZW) {
+            const int rem = K - 32 * q;
+            atomicOr(&c[q], U[g * kw + q] & low_mask(rem));
+        }
+    }
+    __syncthreads();
+    const uint8_t *Cb = (const uint8_t *)C;
+    for (int gg = 0; gg < G; ++gg) {
+        if (f0 + gg >= F)
+            break;
+        for (int64_t b = threadIdx.x; b < nbytes; b += blockDim.x)
+            cw[(f0 + gg) * nbytes + b] = Cb[(size_t)gg * nwo * 4 + b];
+    }
+}
+
+int launch_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, hipStream_t stream)
+{
+    const int ZW = (Z + 31) / 32;
+    int G = kMaxThreads / ZW;
+    G = G < 1 ? 1 : G;
+    const size_t lds = 2 * (size_t)G * (ZW + 1) * 4;
+    hipLaunchKernelGGL(k_shift_packed, dim3((unsigned)((F + G - 1) / G)), dim3(kMaxThreads), lds, stream, in, out,
+                       F, Z, s, G);
+    return check_launch(__func__);
+}
+
+int launch_encode_packed(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream)
+{
+    const int ZW = (sc.Z + 31) / 32;
+    const int per_frame = ((sc.K + 31) / 32 + 1) + 2 * (ZW + 1) + ((sc.N + 31) / 32 + 1);   // words
+    int G = kMaxThreads / ZW;
+    while (G > 1 && (size_t)G * per_frame * 4 > (size_t)kLdsBudget)
+        --G;
+    const size_t lds = (size_t)G * per_frame * 4;
+    hipLaunchKernelGGL(k_encode_packed, dim3((unsigned)((F + G - 1) / G)), dim3(kMaxThreads), lds, stream, sc, G,
+                       info, cw, F);
+    return check_launch(__func__);
+}
+
 }  // namespace ldpc

@@ -237,6 +237,39 @@ int ldpc_encode(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, 
     return device_status(launch_encode(sc, info, cw, F, (hipStream_t)stream), "ldpc_encode");
 }
 
+int ldpc_encode_packed(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *info, uint8_t *cw, int64_t F,
+                       void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, false, &sc);
+    if (rc)
+        return rc;
+    if (sc.enc_y < 0)
+        return fail(LDPC_ESTRUCT, "base matrix lacks the dual-diagonal parity structure of the direct encoder");
+    if (F < 0)
+        return fail(LDPC_EINVAL, "negative frame count");
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({info, cw}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    if ((size_t)((sc.K + 31) / 32 + 1 + 2 * ((sc.Z + 31) / 32 + 1) + (sc.N + 31) / 32 + 1) * 4 > (size_t)kLdsBudget)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the packed encoder's LDS budget", sc.N);
+    return device_status(launch_encode_packed(sc, info, cw, F, (hipStream_t)stream), "ldpc_encode_packed");
+}
+
+int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, void *stream)
+{
+    clear_error();
+    if (F < 0 || Z < 1 || Z > LDPC_MAX_Z || s < 0 || s >= Z)
+        return fail(LDPC_EINVAL, "need F >= 0, 1 <= Z <= %d and 0 <= s < Z", LDPC_MAX_Z);
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({in, out}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_shift_packed(in, out, F, Z, s, (hipStream_t)stream), "ldpc_shift_packed");
+}
+
 int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
                     float alpha, int early_term, const float *w, uint8_t *bits, float *post, int32_t *iters,
                     uint8_t *ok, void *stream)
