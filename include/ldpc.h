@@ -117,6 +117,19 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
                    int32_t *iters, uint8_t *ok, void *stream);
 
 /*
+ * As ldpc_decode_f32 / ldpc_decode_i8, with the hard bits written packed:
+ * bits is device u8 [F][ceil(N/8)], bit n of frame f being bit (n mod 8) of
+ * byte n/8 (the packed layout of ldpc_encode_packed). Needs run-time
+ * specialisation (LDPC_ERANGE if LDPC_JIT=0).
+ */
+int ldpc_decode_f32_packed(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                           float alpha, int early_term, const float *w, uint8_t *bits, float *post, int32_t *iters,
+                           uint8_t *ok, void *stream);
+int ldpc_decode_i8_packed(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                          int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits, int16_t *post,
+                          int32_t *iters, uint8_t *ok, void *stream);
+
+/*
  * Flooding (two-phase) min-sum, for comparison with the layered schedule
  * (Sec. 4, eqs. 18-23 without layering). Each iteration first computes every
  * check row's new messages from the posteriors of the previous iteration

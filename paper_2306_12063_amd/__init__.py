@@ -20,7 +20,7 @@ __all__ = [
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
     "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset",
     "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16",
-    "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
+    "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_decode_f32_packed", "ldpc_decode_i8_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
 ]
 
@@ -60,6 +60,9 @@ EXPORTS = {
     "ldpc_quantize_q16": ([_p, _p, _i64, _f32, _i32, _p], _i32),
     "ldpc_encode_packed": ([_p, _i32, _i32, _i32, _p, _p, _i64, _p], _i32),
     "ldpc_shift_packed": ([_p, _p, _i64, _i32, _i32, _p], _i32),
+    "ldpc_decode_f32_packed": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, _p], _i32),
+    "ldpc_decode_i8_packed": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p],
+                              _i32),
     "ldpc_last_error": ([], C.c_char_p),
     "ldpc_cache_clear": ([], None),
 }
@@ -209,6 +212,53 @@ def ldpc_decode_i8(hbm, Z, llr, max_iter=10, offset=1, wq=0, wq_table=None, earl
                                 int(bool(early_term)), _dev(bits, torch.uint8, "bits", (F, N)),
                                 _opt(post, torch.int16, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
                                 _opt(ok, torch.uint8, "ok", (F,)), _stream(stream)), "ldpc_decode_i8")
+    return bits, post, iters, ok
+
+
+def ldpc_decode_f32_packed(hbm, Z, llr, max_iter=10, alpha=0.75, early_term=True, w=None, bits=None, post=None,
+                           iters=None, ok=None, want_post=False, stream=None):
+    """ldpc_decode_f32 with hard bits packed eight per byte (u8 [F][ceil(N/8)])."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    dev = llr.device
+    nb8 = (N + 7) // 8
+    bits = torch.empty((F, nb8), dtype=torch.uint8, device=dev) if bits is None else bits
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.float32, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+    ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+    _check(lib().ldpc_decode_f32_packed(_hptr(h), Mb, Nb, Z, _dev(llr, torch.float32, "llr", (F, Nb * Z)), F,
+                                        int(max_iter), float(alpha), int(bool(early_term)),
+                                        _opt(w, torch.float32, "w", (max_iter, Mb, Nb)),
+                                        _dev(bits, torch.uint8, "bits", (F, nb8)),
+                                        _opt(post, torch.float32, "post", (F, N)),
+                                        _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)),
+                                        _stream(stream)), "ldpc_decode_f32_packed")
+    return bits, post, iters, ok
+
+
+def ldpc_decode_i8_packed(hbm, Z, llr, max_iter=10, offset=1, wq=0, wq_table=None, early_term=True, bits=None,
+                          post=None, iters=None, ok=None, want_post=False, stream=None):
+    """ldpc_decode_i8 with hard bits packed eight per byte (u8 [F][ceil(N/8)])."""
+    torch = _torch()
+    h = _hbm(hbm)
+    Mb, Nb = h.shape
+    F, N = llr.shape
+    dev = llr.device
+    nb8 = (N + 7) // 8
+    bits = torch.empty((F, nb8), dtype=torch.uint8, device=dev) if bits is None else bits
+    if post is None and want_post:
+        post = torch.empty((F, N), dtype=torch.int16, device=dev)
+    iters = torch.empty(F, dtype=torch.int32, device=dev) if iters is None else iters
+    ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
+    _check(lib().ldpc_decode_i8_packed(_hptr(h), Mb, Nb, Z, _dev(llr, torch.int8, "llr", (F, Nb * Z)), F,
+                                       int(max_iter), int(offset), int(wq),
+                                       _opt(wq_table, torch.uint8, "wq_table", (max_iter, Mb, Nb)),
+                                       int(bool(early_term)), _dev(bits, torch.uint8, "bits", (F, nb8)),
+                                       _opt(post, torch.int16, "post", (F, N)), _dev(iters, torch.int32, "iters", (F,)),
+                                       _opt(ok, torch.uint8, "ok", (F,)), _stream(stream)), "ldpc_decode_i8_packed")
     return bits, post, iters, ok
 
 

@@ -239,16 +239,19 @@ void jit_cache_clear()
 
 // Decode kernel of one code: named after its path and shape so that
 // profiles tell the specialised kernels apart.
-static std::string decode_kernel_name(const Sched &sc, int path)
+static std::string decode_kernel_name(const Sched &sc, int path, bool packed)
 {
     return std::string("ldpc_decode_") + (path == 0 ? "f32" : "i8") + "_z" + std::to_string(sc.Z) + "_mb" +
-           std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb);
+           std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb) + (packed ? "_pk" : "");
 }
 
-static int get_decode_function(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn)
+static int get_decode_function(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn,
+                               bool packed = false)
 {
-    const std::string name = decode_kernel_name(sc, path);
-    return get_function("decode", kJitDecodeSource, prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n",
+    const std::string name = decode_kernel_name(sc, path, packed);
+    return get_function("decode", kJitDecodeSource,
+                        prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n" +
+                            (packed ? "#define LDPC_PACKED 1\n" : ""),
                         name.c_str(), fn);
 }
 
@@ -335,10 +338,10 @@ int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mo
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
-                      const int64_t *Fdev)
+                      const int64_t *Fdev, bool packed)
 {
     hipFunction_t fn;
-    int rc = get_decode_function(sc, lc, path, mode, &fn);
+    int rc = get_decode_function(sc, lc, path, mode, &fn, packed);
     if (rc)
         return rc;
     long long Fll = (long long)F;

@@ -332,6 +332,60 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
                          "ldpc_decode_i8");
 }
 
+int ldpc_decode_f32_packed(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, int64_t F, int max_iter,
+                           float alpha, int early_term, const float *w, uint8_t *bits, float *post, int32_t *iters,
+                           uint8_t *ok, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "packed output needs run-time specialisation (LDPC_JIT=0 is set)");
+    DecodeLaunch lc = jit_default_launch(sc, 0);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    tuned_launch(sc, 0, &lc);
+    return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits, post,
+                             iters, ok, (hipStream_t)stream, nullptr, true);
+}
+
+int ldpc_decode_i8_packed(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr, int64_t F, int max_iter,
+                          int offset, int wq, const uint8_t *wq_table, int early_term, uint8_t *bits, int16_t *post,
+                          int32_t *iters, uint8_t *ok, void *stream)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if ((rc = decode_common_checks(sc, F, max_iter)))
+        return rc;
+    if (offset < 0 || offset > 127)
+        return fail(LDPC_EINVAL, "offset must be in [0, 127] (got %d)", offset);
+    if (wq < 0 || wq > 31)
+        return fail(LDPC_EINVAL, "wq must be in [0, 31] (got %d)", wq);
+    if (F == 0)
+        return LDPC_OK;
+    if (bad_ptrs({llr, bits, iters}))
+        return fail(LDPC_EINVAL, "null device pointer (llr, bits and iters are required)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "packed output needs run-time specialisation (LDPC_JIT=0 is set)");
+    DecodeLaunch lc = jit_default_launch(sc, 1);
+    if (lc.G < 1)
+        return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
+    tuned_launch(sc, 1, &lc);
+    return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset, wq,
+                             early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream, nullptr, true);
+}
+
 static int flood_common(const int16_t *hbm, int Mb, int Nb, int Z, const void *llr, int64_t F, int max_iter,
                         const void *bits, const int32_t *iters, Sched *sc, DecodeLaunch *lc)
 {

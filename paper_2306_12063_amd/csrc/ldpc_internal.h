@@ -102,7 +102,7 @@ int launch_jit_q16(const Sched &sc, const DecodeLaunch &lc, int wrap, const int1
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
                       const int64_t *fidx, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
-                      const int64_t *Fdev = nullptr);
+                      const int64_t *Fdev = nullptr, bool packed = false);
 
 // Learned normalised min-sum training kernels (jit.cpp, jit_nms.hip).
 size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T);

@@ -63,3 +63,26 @@ def test_encode_packed_agrees_with_byte_encoder_at_scale():
     packed = _gpu(_pack(bits.cpu().numpy()))
     got = P.ldpc_encode_packed(h, 81, packed).cpu().numpy()
     assert np.array_equal(got, _pack(cw))
+
+
+@pytest.mark.parametrize("code", [("wifi", "1/2", 81), ("wimax", "5/6", 96), ("tiny", None, 3)])
+def test_decode_packed_bits(code):
+    # hard bits packed eight per byte equal the unpacked decode's bits, packed
+    kind, rate, Z = code
+    if kind == "tiny":
+        h = np.array([[0, 1, 2, 0, -1], [2, -1, 0, 1, 0]], np.int16)   # N = 15: a partial last byte
+        llr = RNG.normal(0.5, 2.0, (37, 15)).astype(np.float32)
+    else:
+        h = synth.wifi_code(rate, Z) if kind == "wifi" else synth.wimax_code(rate, Z)
+        _, _, llr = oracle.llr_frames(h, Z, 37, 2.5, 4)
+    for et in (True, False):
+        b, _, it, ok = P.ldpc_decode_f32(h, Z, _gpu(llr), max_iter=7, early_term=et)
+        bp, _, itp, okp = P.ldpc_decode_f32_packed(h, Z, _gpu(llr), max_iter=7, early_term=et)
+        assert np.array_equal(bp.cpu().numpy(), _pack(b.cpu().numpy()))
+        assert torch.equal(it, itp) and torch.equal(ok, okp)
+        q = _gpu(oracle.quantize_i8(llr))
+        b, _, it, _ = P.ldpc_decode_i8(h, Z, q, max_iter=7, offset=1, early_term=et)
+        bp, post, itp, _ = P.ldpc_decode_i8_packed(h, Z, q, max_iter=7, offset=1, early_term=et, want_post=True)
+        assert np.array_equal(bp.cpu().numpy(), _pack(b.cpu().numpy())) and torch.equal(it, itp)
+        _, want_post, _, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(llr), max_iter=7, offset=1, early_term=et)
+        assert np.array_equal(post.cpu().numpy(), want_post)
