@@ -25,7 +25,7 @@ GPU = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-pack
 
 JIT_SOURCES = [("jit_decode.hip", "kJitDecodeSource"), ("jit_nms.hip", "kJitNmsSource"),
                ("jit_batch.hip", "kJitBatchSource"), ("jit_flood.hip", "kJitFloodSource"),
-               ("jit_q16.hip", "kJitQ16Source")]
+               ("jit_q16.hip", "kJitQ16Source"), ("jit_h2.hip", "kJitH2Source")]
 
 
 def _embed_jit_source():

@@ -27,6 +27,7 @@ extern const char kJitNmsSource[];
 extern const char kJitBatchSource[];
 extern const char kJitFloodSource[];
 extern const char kJitQ16Source[];
+extern const char kJitH2Source[];
 
 namespace {
 
@@ -239,17 +240,18 @@ void jit_cache_clear()
 
 // Decode kernel of one code: named after its path and shape so that
 // profiles tell the specialised kernels apart.
-static std::string decode_kernel_name(const Sched &sc, int path, bool packed)
+static std::string decode_kernel_name(const Sched &sc, int path, bool packed, bool h2)
 {
-    return std::string("ldpc_decode_") + (path == 0 ? "f32" : "i8") + "_z" + std::to_string(sc.Z) + "_mb" +
-           std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb) + (packed ? "_pk" : "");
+    return std::string("ldpc_decode_") + (path == 0 ? "f32" : (h2 ? "i8h2" : "i8")) + "_z" + std::to_string(sc.Z) +
+           "_mb" + std::to_string(sc.Mb) + "_nb" + std::to_string(sc.Nb) + (packed ? "_pk" : "");
 }
 
 static int get_decode_function(const Sched &sc, const DecodeLaunch &lc, int path, int mode, hipFunction_t *fn,
                                bool packed = false)
 {
-    const std::string name = decode_kernel_name(sc, path, packed);
-    return get_function("decode", kJitDecodeSource,
+    const bool h2 = lc.h2 != 0;
+    const std::string name = decode_kernel_name(sc, path, packed, h2);
+    return get_function(h2 ? "decode_h2" : "decode", h2 ? kJitH2Source : kJitDecodeSource,
                         prelude(sc, lc, path, mode) + "#define LDPC_KERNEL " + name + "\n" +
                             (packed ? "#define LDPC_PACKED 1\n" : ""),
                         name.c_str(), fn);
@@ -313,13 +315,70 @@ int launch_jit_q16(const Sched &sc, const DecodeLaunch &lc, int wrap, const int1
     return launch(fn, (unsigned)((F + lc.FW - 1) / lc.FW), lc.threads, stream, args, "q16 decode");
 }
 
+// One frame per thread, FP32 posteriors in LDS (both paths).
+static DecodeLaunch single_frame_launch(const Sched &sc)
+{
+    DecodeLaunch lc = plan_decode(sc, 4, 1);
+    lc.hoist = 2 * (sc.E / sc.Z) <= 176 ? sc.Mb : 0;
+    return lc;
+}
+
+int max_col_weight(const Sched &sc)
+{
+    int w[64] = {0}, best = 0;
+    for (int i = 0; i < sc.Mb; ++i)
+        for (int e = 0; e < sc.deg[i]; ++e) {
+            const int j = (int)(sc.edge[i][e] >> 16);
+            if (j < 64)
+                best = std::max(best, ++w[j]);
+        }
+    return best;
+}
+
+DecodeLaunch make_h2_launch(const Sched &sc, int G, int max_threads)
+{
+    DecodeLaunch lc{};
+    if (G < 1 || 2 * G > 64 || G * sc.Z > max_threads)
+        return lc;
+    const int FWp = G | 1;
+    const size_t lds = (size_t)(sc.N + sc.Z) * FWp * 4;
+    if (lds > (size_t)kLdsBudget)
+        return lc;
+    lc = DecodeLaunch{G, 1, 2 * G, FWp, ((G * sc.Z + 63) / 64) * 64, lds, 0};
+    lc.h2 = 1;
+    return lc;
+}
+
+DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
+{
+    if (lc.h2 && (path != 1 || mode == 2 || !h2_eligible(sc)))
+        return single_frame_launch(sc);
+    return lc;
+}
+
 DecodeLaunch jit_default_launch(const Sched &sc, int path)
 {
-    DecodeLaunch lc = plan_decode(sc, 4, 1);   // FP32 posteriors in LDS on both paths
-    (void)path;
     const int per_row = sc.E / sc.Z;          // messages (and gather addresses) per thread
-    lc.hoist = 2 * per_row <= 176 ? sc.Mb : 0;
-    return lc;
+    if (path == 1 && h2_eligible(sc)) {
+        // fixed point: two frames per lane; the widest workgroup with the most busy lanes
+        DecodeLaunch best{};
+        double best_util = -1.0;
+        for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
+            const DecodeLaunch lc = make_h2_launch(sc, G, kMaxThreads);
+            if (lc.G < 1)
+                break;
+            const double util = (double)(G * sc.Z) / lc.threads;
+            if (util > best_util + 1e-9 || (util > best_util - 1e-9 && lc.FW > best.FW)) {
+                best_util = util;
+                best = lc;
+            }
+        }
+        if (best.G >= 1) {
+            best.hoist = 2 * per_row <= 176 ? sc.Mb : 0;
+            return best;
+        }
+    }
+    return single_frame_launch(sc);
 }
 
 int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes)
@@ -340,6 +399,8 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
                       const int64_t *Fdev, bool packed)
 {
+    if (lc.h2 && (path != 1 || mode == 2))
+        return fail(LDPC_EINVAL, "internal: a two-frames-per-lane layout was chosen for path %d mode %d", path, mode);
     hipFunction_t fn;
     int rc = get_decode_function(sc, lc, path, mode, &fn, packed);
     if (rc)

@@ -1,0 +1,307 @@
+// Fixed-point layered min-sum with two frames per lane in packed FP16,
+// specialised for one code at run time (prelude of jit_decode.hip, with
+// LDPC_G frame PAIRS per workgroup and LDPC_KF 1).
+//
+// The fixed-point path works on integers of magnitude at most 127 * (1 +
+// column weight) (int8 messages, |L| bounded by the channel value plus the
+// messages of its column), so for codes whose column weight is at most 15
+// every value is below 2048 and exact in FP16. One 32-bit register then
+// holds the same quantity for two frames: posteriors in LDS (element (n, p)
+// at PAD + n*FWP + p holds frames 2p, 2p+1), the message of every edge of
+// the thread's rows, and all per-edge arithmetic, which is the update of
+// jit_decode.hip on pairs:
+//   Q = L - R (v_pk_add_f16);  |Q| = Q & 0x7fff7fff;  min1/min2 as unsigned
+//   16-bit min/max of the magnitudes' bit patterns (non-negative FP16 values
+//   order as their bits);  sign parity = XOR of the Q words (bits 15, 31);
+//   magnitude = |Q| == min1 ? n2 : n1 as n2 + min(|Q| - min1, 1) * (n1 - n2)
+//   on 16-bit lanes (v_pk_mad_u16);  R = (Q & 0x80008000) ^ magnitude (the
+//   parity is in the magnitude's sign bits);  L = Q + R (v_pk_add_f16).
+// A frame that stops (early termination) has its outputs written at once;
+// its half of the pair then keeps being updated but is no longer tested or
+// written, so the per-edge work needs no mask. Per-row magnitude rules (offset, or wq/16 in
+// FP32) are those of the int8 definition; results are bit-identical to it.
+
+#ifndef LDPC_PACKED
+#define LDPC_PACKED 0
+#endif
+
+typedef unsigned char u8;
+typedef unsigned int u32;
+typedef long long i64;
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+constexpr int Z = LDPC_Z, MB = LDPC_MB, NB = LDPC_NB, N = LDPC_N, MAXD = LDPC_MAXD;
+constexpr int G = LDPC_G, FWP = LDPC_FWP;
+constexpr int FW = 2 * G;
+constexpr int ZFW = Z * FWP;
+constexpr int PAD = ZFW;
+
+constexpr int row_edges()
+{
+    int s = 0;
+    for (int i = 0; i < MB; ++i)
+        s += kDeg[i];
+    return s;
+}
+constexpr int edge_off(int i)
+{
+    int s = 0;
+    for (int k = 0; k < i; ++k)
+        s += kDeg[k];
+    return s;
+}
+constexpr int ED = row_edges();
+
+template <int V>
+struct Int {
+    static constexpr int value = V;
+};
+template <int I, int Nn, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f)
+{
+    if constexpr (I < Nn) {
+        f(Int<I>());
+        static_for<I + 1, Nn>(f);
+    }
+}
+
+__device__ __forceinline__ int gather_b(int i, int e, int r, int rbn_b, int rbw_b)
+{
+    return ((r >= Z - kShift[i][e]) ? rbw_b : rbn_b) + (kCol[i][e] * Z + kShift[i][e]) * FWP * 4;
+}
+
+__device__ __forceinline__ h2 H(u32 x) { return __builtin_bit_cast(h2, x); }
+__device__ __forceinline__ u2 V(u32 x) { return __builtin_bit_cast(u2, x); }
+__device__ __forceinline__ u32 W(h2 x) { return __builtin_bit_cast(u32, x); }
+__device__ __forceinline__ u32 W(u2 x) { return __builtin_bit_cast(u32, x); }
+
+__device__ __forceinline__ u32 ldb(const u32 *Ls, int b) { return *(const u32 *)((const char *)Ls + b); }
+__device__ __forceinline__ void stb(u32 *Ls, int b, u32 v) { *(u32 *)((char *)Ls + b) = v; }
+
+// hard decisions of a pair (bit 0: frame 2p, bit 16: frame 2p+1): 1 where
+// the value is <= 0, i.e. where its bits as int16 are <= 0 (no -0 occurs)
+__device__ __forceinline__ u32 hard_bits(u32 x)
+{
+    const u2 one = {1, 1};
+    return W((V(x) - one) >> (u2){15, 15});
+}
+
+__device__ __forceinline__ float norm_mag(float w, float m)
+{
+    return __builtin_fminf(127.0f, __builtin_floorf((w * m + 8.0f) * 0.0625f));
+}
+
+extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
+    const signed char *__restrict__ llr, const i64 *__restrict__ fidx, const i64 Fmax, const int max_iter,
+    const float alpha, const int offset, const int wq, const int et, const u8 *__restrict__ wt,
+    u8 *__restrict__ bits, short *__restrict__ post, int *__restrict__ iters, u8 *__restrict__ okv,
+    const i64 *__restrict__ Fdev)
+{
+    const i64 F = Fdev ? (*Fdev < Fmax ? *Fdev : Fmax) : Fmax;
+    if ((i64)blockIdx.x * FW >= F)
+        return;
+    __shared__ u32 Ls[PAD + N * FWP];
+    __shared__ int unsat[FW];
+    const int tid = threadIdx.x;
+    const int g = tid / Z;
+    const int r = tid - g * Z;
+    const bool lane_on = g < G;
+    const i64 f0 = (i64)blockIdx.x * FW;
+    _Float16 *Lh = (_Float16 *)Ls;
+    for (int slot = 0; slot < FW; ++slot) {
+        const i64 fg = f0 + slot;
+        const bool real = fg < F;
+        const signed char *p = real ? llr + (fidx ? fidx[fg] : fg) * (i64)N : nullptr;
+        for (int n = tid; n < N; n += LDPC_THREADS)
+            Lh[2 * (PAD + n * FWP + (slot >> 1)) + (slot & 1)] = real ? (_Float16)(float)p[n] : (_Float16)0.0f;
+    }
+    __shared__ int conv[FW];
+    if (tid < FW) {
+        unsat[tid] = 0;
+        conv[tid] = 0;
+    }
+    const bool act0 = lane_on && f0 + 2 * g < F, act1 = lane_on && f0 + 2 * g + 1 < F;
+    bool act[2] = {act0, act1};
+    int itk[2] = {max_iter, max_iter}, okk[2] = {0, 0};
+    u32 R[ED];
+#pragma unroll
+    for (int e = 0; e < ED; ++e)
+        R[e] = 0u;
+    u32 one = 0x00010001u;
+    asm volatile("" : "+v"(one));   // keeps min(d, 1) * D as a multiply-add
+    const u32 beta = W((h2){(_Float16)(float)offset, (_Float16)(float)offset});
+    const float wqf = (float)wq;
+    __syncthreads();
+
+    // outputs of frame slot `slot` (bits, posteriors) from LDS, by the whole workgroup
+    auto write_frame = [&](int slot) {
+        const i64 fg = f0 + slot;
+        if (fg >= F)
+            return;
+        const i64 row = fidx ? fidx[fg] : fg;
+        const int hsel = slot & 1, pair = slot >> 1;
+#if LDPC_PACKED
+        constexpr int NB8 = (N + 7) / 8;
+        for (int b = tid; b < NB8; b += LDPC_THREADS) {
+            u32 byte = 0;
+#pragma unroll
+            for (int tt = 0; tt < 8; ++tt)
+                if (8 * b + tt < N)
+                    byte |= ((float)Lh[2 * (PAD + (8 * b + tt) * FWP + pair) + hsel] > 0.0f ? 0u : 1u) << tt;
+            bits[row * NB8 + b] = (u8)byte;
+        }
+        if (post)
+            for (int n = tid; n < N; n += LDPC_THREADS)
+                post[row * N + n] = (short)(float)Lh[2 * (PAD + n * FWP + pair) + hsel];
+#else
+        for (int n = tid; n < N; n += LDPC_THREADS) {
+            const float v = (float)Lh[2 * (PAD + n * FWP + pair) + hsel];
+            bits[row * N + n] = v > 0.0f ? 0 : 1;
+            if (post)
+                post[row * N + n] = (short)v;
+        }
+#endif
+    };
+
+    for (int t = 0; t < max_iter; ++t) {
+        const bool check = et || (t == max_iter - 1);
+        const bool live = lane_on && (f0 + 2 * g < F);   // the pair holds at least one frame
+        u32 lastbad = 0;
+        static_for<0, MB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int d = kDeg[i];
+            constexpr int eo = edge_off(i);
+            int rr = r;
+            if constexpr (i >= LDPC_HOIST)
+                asm volatile("" : "+v"(rr));
+            const int rbw = (rr * FWP + g) * 4, rbn = rbw + PAD * 4;
+            if (live) {
+                int ix[MAXD];
+                u32 Q[MAXD];
+#pragma unroll
+                for (int e = 0; e < d; ++e) {
+                    ix[e] = gather_b(i, e, rr, rbn, rbw);
+                    Q[e] = W(H(ldb(Ls, ix[e])) - H(R[eo + e]));
+                }
+                u2 m1 = {0x7fff, 0x7fff}, m2 = m1;
+                u32 px = 0;
+#pragma unroll
+                for (int e = 0; e < d; ++e) {
+                    const u2 a = V(Q[e] & 0x7fff7fffu);
+                    m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, a));
+                    m1 = __builtin_elementwise_min(m1, a);
+                    px ^= Q[e];
+                }
+                const u32 par = px & 0x80008000u;
+                const u2 cap = {0x57f0, 0x57f0};   // 127.0 in FP16
+                const u32 c1 = W(__builtin_elementwise_min(m1, cap)), c2 = W(__builtin_elementwise_min(m2, cap));
+                u32 n1, n2;
+#if LDPC_MODE == 0
+                {
+                    // max(c - offset, 0): negative FP16 values are negative as int16
+                    typedef short s2 __attribute__((ext_vector_type(2)));
+                    const s2 z = {0, 0};
+                    n1 = __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s2, W(H(c1) - H(beta))), z));
+                    n2 = __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s2, W(H(c2) - H(beta))), z));
+                }
+#else
+                {
+                    const h2 a1 = H(c1), a2 = H(c2);
+                    const h2 b1 = {(_Float16)norm_mag(wqf, (float)a1.x), (_Float16)norm_mag(wqf, (float)a1.y)};
+                    const h2 b2 = {(_Float16)norm_mag(wqf, (float)a2.x), (_Float16)norm_mag(wqf, (float)a2.y)};
+                    n1 = W(b1);
+                    n2 = W(b2);
+                }
+#endif
+                u32 n2p = n2 | par;
+                u32 dlt = W(V(n1 | par) - V(n2p));
+                asm volatile("" : "+v"(n2p), "+v"(dlt));
+                u32 bad = 0;
+#pragma unroll
+                for (int e = 0; e < d; ++e) {
+                    const u2 a = V(Q[e] & 0x7fff7fffu);
+                    const u2 c = __builtin_elementwise_min(a - m1, V(one));        // 0 at the minimum, else 1
+                    const u32 mag = W(c * V(dlt) + V(n2p));                        // n2p or n1p
+                    const u32 rv = (Q[e] & 0x80008000u) ^ mag;
+                    R[eo + e] = rv;
+                    const u32 lv = W(H(Q[e]) + H(rv));
+                    stb(Ls, ix[e], lv);
+                    if (i == MB - 1)
+                        bad ^= hard_bits(lv);
+                }
+                if (i == MB - 1)
+                    lastbad = bad;
+            }
+            __syncthreads();
+        });
+        if (check) {
+            u32 bad = lastbad;
+            if (act[0] || act[1]) {
+                static_for<0, MB - 1>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    int rr = r;
+                    if constexpr (i >= LDPC_HOIST)
+                        asm volatile("" : "+v"(rr));
+                    const int rbw = (rr * FWP + g) * 4, rbn = rbw + PAD * 4;
+                    u32 p = 0;
+#pragma unroll
+                    for (int e = 0; e < kDeg[i]; ++e)
+                        p ^= hard_bits(ldb(Ls, gather_b(i, e, rr, rbn, rbw)));
+                    bad |= p;
+                });
+                if (act[0] && (bad & 1u))
+                    unsat[2 * g] = 1;
+                if (act[1] && (bad & 0x10000u))
+                    unsat[2 * g + 1] = 1;
+            }
+            __syncthreads();
+            int any = 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (act[k]) {
+                    const int sat = unsat[2 * g + k] == 0;
+                    if (t == max_iter - 1)
+                        okk[k] = sat;
+                    if (et && sat) {
+                        act[k] = false;
+                        itk[k] = t + 1;
+                        okk[k] = 1;
+                        if (r == 0)
+                            conv[2 * g + k] = 1;
+                    }
+                }
+                any |= act[k];
+            }
+            __syncthreads();
+            if (tid < FW)
+                unsat[tid] = 0;
+            // frames that stopped in this iteration: outputs now (their
+            // halves are not written back later)
+            for (int slot = 0; slot < FW; ++slot)
+                if (conv[slot] == 1)
+                    write_frame(slot);
+            __syncthreads();
+            if (tid < FW && conv[tid] == 1)
+                conv[tid] = 2;
+            if (et && !__syncthreads_or(any))
+                break;
+        }
+    }
+    __syncthreads();
+    if (lane_on && r == 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const i64 fg = f0 + 2 * g + k;
+            if (fg < F) {
+                const i64 row = fidx ? fidx[fg] : fg;
+                iters[row] = itk[k];
+                if (okv)
+                    okv[row] = (u8)okk[k];
+            }
+        }
+    }
+    for (int slot = 0; slot < FW; ++slot)
+        if (conv[slot] == 0)
+            write_frame(slot);
+}

@@ -291,6 +291,7 @@ int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr,
     if (jit_enabled()) {
         lc = jit_default_launch(sc, 0);
         tuned_launch(sc, 0, &lc);
+        lc = usable_launch(sc, lc, 0, w ? 1 : 0);
         return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits,
                                  post, iters, ok, (hipStream_t)stream);
     }
@@ -324,6 +325,7 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
     if (jit_enabled()) {
         lc = jit_default_launch(sc, 1);
         tuned_launch(sc, 1, &lc);
+        lc = usable_launch(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
         return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset,
                                  wq, early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream);
     }
@@ -353,6 +355,7 @@ int ldpc_decode_f32_packed(const int16_t *hbm, int Mb, int Nb, int Z, const floa
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     tuned_launch(sc, 0, &lc);
+    lc = usable_launch(sc, lc, 0, w ? 1 : 0);
     return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits, post,
                              iters, ok, (hipStream_t)stream, nullptr, true);
 }
@@ -382,6 +385,7 @@ int ldpc_decode_i8_packed(const int16_t *hbm, int Mb, int Nb, int Z, const int8_
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     tuned_launch(sc, 1, &lc);
+    lc = usable_launch(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
     return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset, wq,
                              early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream, nullptr, true);
 }
@@ -438,7 +442,7 @@ int ldpc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t
 }
 
 int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
-                         int32_t out[5], float *ms, void *stream)
+                         int32_t out[6], float *ms, void *stream)
 {
     clear_error();
     Sched sc;
@@ -461,6 +465,7 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
     out[2] = best.FWp;
     out[3] = best.threads;
     out[4] = best.hoist;
+    out[5] = best.h2;
     return LDPC_OK;
 }
 
@@ -582,9 +587,10 @@ int fallback(const int16_t *hbm, int Mb, int Nb, int Z, int path, const void *ll
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     tuned_launch(sc, path, &lc);
+    const int mode = path == 0 ? 0 : (wq > 0 ? 1 : 0);
+    lc = usable_launch(sc, lc, path, mode);
     if ((rc = launch_compact_failed(ok, F, work, stream)))
         return device_status(rc, "fallback compaction");
-    const int mode = path == 0 ? 0 : (wq > 0 ? 1 : 0);
     return launch_jit_decode(sc, lc, path, mode, llr, work + 1, F, max_iter, alpha, offset, wq, 1, nullptr, bits, post,
                              iters, ok, stream, work);
 }

@@ -56,7 +56,20 @@ struct DecodeLaunch {
     int threads; // workgroup size
     size_t lds;  // LDS bytes of the posteriors
     int hoist = 0;  // specialised kernels: block rows whose gather addresses stay in registers
+    int h2 = 0;     // fixed point with two frames per lane in packed FP16 (G = frame pairs, FW = 2G)
 };
+
+// Largest column weight (block rows with an edge in a block column).
+int max_col_weight(const Sched &sc);
+// Whether the packed-FP16 fixed-point kernel applies: its values, at most
+// 127 * (1 + column weight), must be exact in FP16 (<= 2048).
+inline bool h2_eligible(const Sched &sc) { return max_col_weight(sc) <= 15; }
+// A layout with G frame pairs per workgroup for the packed-FP16 kernel
+// (G < 1 if it does not fit).
+DecodeLaunch make_h2_launch(const Sched &sc, int G, int max_threads);
+// The layout to use for (path, mode): a packed-FP16 layout is replaced by
+// the default one where it does not apply (FP32, weight tables).
+DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode);
 
 // Kernel launchers (decode_kernels.hip). Return LDPC_OK or LDPC_EDEVICE.
 int launch_decode_f32(const Sched &sc, const DecodeLaunch &lc, const float *llr, const int64_t *fidx, int64_t F,

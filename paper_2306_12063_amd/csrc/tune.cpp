@@ -39,11 +39,27 @@ std::string tune_key(const Sched &sc, int path)
 // per hoisted edge; the registers decide how many waves share a SIMD, which
 // is hard to predict, so the candidates are compiled and timed, and those
 // that spill are dropped.
-std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes)
+std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
 {
     std::vector<DecodeLaunch> out;
     const int per_row = sc.E / sc.Z;
     const int hoists[4] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, 0};
+    // fixed point: two frames per lane in packed FP16 where the values fit
+    if (path == 1 && h2_eligible(sc)) {
+        for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
+            DecodeLaunch lc = make_h2_launch(sc, G, kMaxThreads);
+            if (lc.G < 1 || (double)(G * sc.Z) / lc.threads < 0.85)
+                continue;
+            int last = -1;
+            for (int h : hoists) {
+                if (h == last)
+                    continue;
+                last = h;
+                lc.hoist = h;
+                out.push_back(lc);
+            }
+        }
+    }
     for (int KF = 1; KF <= 2 && KF * per_row <= 200; ++KF) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
             DecodeLaunch lc = make_launch(sc, elem_bytes, G, KF, kMaxThreads);
@@ -110,7 +126,7 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         rc = fail(LDPC_EDEVICE, "autotune: HIP setup failed");
         goto done;
     }
-    for (const DecodeLaunch &lc : candidates(sc, eb)) {
+    for (const DecodeLaunch &lc : candidates(sc, eb, path)) {
         size_t scratch = 0;
         if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch)))
             goto done;
