@@ -270,8 +270,9 @@ def main():
         hbm_b = F * (in_b + c["N"] + 4 + 1)          # LLRs in; bits, iterations, ok out
         lds_b = F * lds_model_bytes(c["path"], c["E"], c["M"], ITERS)
         mb = c["hbm"].shape[0]
+        kpath = "i8h2" if layouts.get(f"{c['path']} {c['rate']}", {}).get("h2") else c["path"]
         per.append(dict(kernel=f"decode_{c['path']}", rate=c["rate"],
-                        name=f"ldpc_decode_{c['path']}_z{Z}_mb{mb}_nb24", ms=ms,
+                        name=f"ldpc_decode_{kpath}_z{Z}_mb{mb}_nb24", ms=ms,
                         gbit_s=F * c["K"] / (ms / 1e3) / 1e9,
                         valu_tops=ops / (ms / 1e3) / 1e12, hbm_gbs=hbm_b / (ms / 1e3) / 1e9,
                         lds_model_gbs=lds_b / (ms / 1e3) / 1e9,
