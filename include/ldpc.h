@@ -297,8 +297,9 @@ int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const i
  * persistent kernel). Decodes the caller's batch -- same arguments as
  * ldpc_decode_batch_f32/_i8 for `path` 0/1 -- with alpha 0.75 (FP32) or
  * offset 1 (int8), early termination off, under each candidate layout:
- * workgroups of 256 or 512 threads, each code's work items holding
- * floor(threads / Z) or half as many frames (at most 64). Keeps the fastest
+ * workgroups of 192, 256, 384 or 512 threads, each code's work items
+ * holding floor(threads / Z) frames (at most 64), and for 256 and 512
+ * threads also half as many. Keeps the fastest
  * for later batched decodes of `path` with this code set; out[2] receives
  * {threads, divisor} and *ms its time per decode. bits and iters receive the
  * last decode's results. Synchronises `stream`; the code set must not be in

@@ -5,7 +5,7 @@
 // the persistent kernel of jit_batch.hip is compiled once per code set with
 // each class's degrees and columns as constants, and reads each code's Z,
 // shifts and layout from the device tables built here. A batched decode is
-// five stream-ordered kernels (clear, histogram by code, plan of work items,
+// six stream-ordered kernels (clear, histogram by code, plan, work items,
 // scatter of frame indices, persistent decode) with no host synchronisation,
 // so a caller may capture it in a hipGraph.
 #include <stdio.h>
@@ -192,11 +192,19 @@ int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, cons
     return LDPC_OK;
 }
 
-// Work buffer: head (items, queue, hist[ncodes], cursor[ncodes]), perm[F]
-// (padded to an even count so the items stay 16-byte aligned), items[F + ncodes].
+// Work buffer (int64 words): head = items, queue, hist[ncodes],
+// cursor[ncodes], ibase[ncodes] (padded to an even count); perm[F] (frame
+// ids grouped by code); offp[F] (their offsets); then items[F + ncodes]
+// (int4, 16-byte aligned).
+static int64_t head_words(int ncodes)
+{
+    const int64_t h = 2 + 3 * (int64_t)ncodes;
+    return h + (h & 1);
+}
+
 size_t batch_work_bytes(const ldpc_codeset *cs, int64_t F)
 {
-    return (size_t)(2 + 2 * cs->ncodes + F + (F & 1)) * sizeof(int64_t) + (size_t)(F + cs->ncodes) * 4 * sizeof(int);
+    return (size_t)(head_words(cs->ncodes) + 2 * F) * sizeof(int64_t) + (size_t)(F + cs->ncodes) * 4 * sizeof(int);
 }
 
 int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_t *code_id, const int64_t *off,
@@ -204,28 +212,36 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
                         uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, void *work, hipStream_t stream)
 {
     const std::string pre = batch_prelude(*cs, path, mode);
-    hipFunction_t f_clear, f_hist, f_plan, f_scatter, f_dec;
+    hipFunction_t f_clear, f_hist, f_plan, f_items, f_scatter, f_dec;
     int rc;
     if ((rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_clear", &f_clear)) ||
         (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_hist", &f_hist)) ||
         (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_plan", &f_plan)) ||
+        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_items", &f_items)) ||
         (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_scatter", &f_scatter)) ||
         (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_decode", &f_dec)))
         return rc;
+    const int64_t hw = head_words(cs->ncodes);
     int64_t *head = (int64_t *)work;
-    int64_t *perm = head + 2 + 2 * cs->ncodes;
-    int *items = (int *)(perm + F + (F & 1));
+    int64_t *perm = head + hw;
+    int64_t *offp = perm + F;
+    int *items = (int *)(offp + F);
     int nc = cs->ncodes;
+    int nwords = (int)hw;
     long long Fll = (long long)F;
     const void *codes = cs->d_codes[path], *etab = cs->d_etab[path];
-    void *a_clear[] = {(void *)&head, (void *)&nc};
+    void *a_clear[] = {(void *)&head, (void *)&nwords};
     void *a_hist[] = {(void *)&code_id, (void *)&Fll, (void *)&nc, (void *)&head};
-    void *a_plan[] = {(void *)&codes, (void *)&nc, (void *)&head, (void *)&items};
-    void *a_scatter[] = {(void *)&code_id, (void *)&Fll, (void *)&nc, (void *)&head, (void *)&perm};
-    const unsigned fblocks = (unsigned)((F + 255) / 256);
-    if ((rc = jit_launch(f_clear, (unsigned)((2 + 2 * nc + 255) / 256), 256, stream, a_clear, "batch clear")) ||
+    void *a_plan[] = {(void *)&codes, (void *)&nc, (void *)&head};
+    void *a_items[] = {(void *)&codes, (void *)&nc, (void *)&head, (void *)&items};
+    void *a_scatter[] = {(void *)&code_id, (void *)&off,  (void *)&Fll,
+                         (void *)&nc,      (void *)&head, (void *)&perm, (void *)&offp};
+    // frames per workgroup of the histogram and the scatter (FPB in jit_batch.hip)
+    const unsigned fblocks = (unsigned)((F + 4095) / 4096);
+    if ((rc = jit_launch(f_clear, (unsigned)((nwords + 255) / 256), 256, stream, a_clear, "batch clear")) ||
         (rc = jit_launch(f_hist, fblocks, 256, stream, a_hist, "batch histogram")) ||
         (rc = jit_launch(f_plan, 1, 1024, stream, a_plan, "batch plan")) ||
+        (rc = jit_launch(f_items, (unsigned)nc, 256, stream, a_items, "batch items")) ||
         (rc = jit_launch(f_scatter, fblocks, 256, stream, a_scatter, "batch scatter")))
         return rc;
     // persistent grid: as many workgroups as can be resident at once
@@ -236,7 +252,7 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
     const unsigned grid = (unsigned)std::max(1, per_cu * cus);
     int64_t *nitems = head;
     unsigned long long *queue = (unsigned long long *)(head + 1);
-    void *a_dec[] = {(void *)&items, (void *)&nitems, (void *)&queue, (void *)&perm, (void *)&off, (void *)&codes,
+    void *a_dec[] = {(void *)&items, (void *)&nitems, (void *)&queue, (void *)&perm, (void *)&offp, (void *)&codes,
                      (void *)&etab, (void *)&llr, (void *)&max_iter, (void *)&alpha, (void *)&offset, (void *)&wq,
                      (void *)&et, (void *)&bits, (void *)&post, (void *)&iters, (void *)&ok};
     return jit_launch(f_dec, grid, cs->threads[path], stream, a_dec, "batch decode");
@@ -248,7 +264,8 @@ int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const i
                      int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, hipStream_t stream,
                      int32_t out[2], float *best_ms)
 {
-    static const int cand[4][2] = {{256, 1}, {512, 1}, {256, 2}, {512, 2}};
+    static const int cand[][2] = {{256, 1}, {192, 1}, {384, 1}, {512, 1}, {256, 2}, {512, 2}};
+    constexpr int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)
@@ -259,7 +276,7 @@ int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const i
     float best_t = 1e30f;
     const char *lv = getenv("LDPC_TUNE_LOG");
     const bool log = lv && lv[0] == '1';
-    for (int k = 0; k < 4 && rc == LDPC_OK; ++k) {
+    for (int k = 0; k < ncand && rc == LDPC_OK; ++k) {
         if ((rc = build_tables(cs, path, cand[k][0], cand[k][1])))
             break;
         auto run = [&]() {

@@ -157,7 +157,7 @@ def test_batch_autotune_keeps_parity():
     for path in ("f32", "i8"):
         src = d(llr) if path == "f32" else d(q)
         cfg = cs.autotune(path, d(cid), d(off), src, max_iter=6)
-        assert cfg["threads"] in (256, 512) and cfg["divisor"] in (1, 2) and cfg["ms"] > 0
+        assert cfg["threads"] in (192, 256, 384, 512) and cfg["divisor"] in (1, 2) and cfg["ms"] > 0
         if path == "f32":
             bits, post, iters, ok = cs.decode_f32(d(cid), d(off), src, max_iter=6, alpha=0.75, early_term=True)
         else:
@@ -174,3 +174,48 @@ def test_batch_autotune_keeps_parity():
             for k, f in enumerate(idx):
                 assert np.array_equal(bits[off[f]:off[f] + N], wb[k]) and np.array_equal(post[off[f]:off[f] + N], wp[k])
             assert np.array_equal(iters[idx], wi)
+
+
+def test_batch_grouping_one_dominant_code():
+    # Frames of a batch are grouped by code in per-workgroup LDS counts with
+    # one global count per code and workgroup: here most of 9000 frames (three
+    # such workgroups) share one code, some carry invalid code ids (their
+    # outputs must stay untouched), and one code has N < 256, so a thread's
+    # share of a work item spans several frames.
+    codes = [("1/2", 8, synth.wimax_code("1/2", 8, seed=4)), ("5/6", 24, synth.wimax_code("5/6", 24, seed=5)),
+             ("3/4A", 52, synth.wimax_code("3/4A", 52, seed=6))]
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    F = 9000
+    rng = np.random.default_rng(21)
+    cid = np.where(rng.random(F) < 0.9, 1, rng.integers(-1, 4, F)).astype(np.int32)   # -1 and 3 are invalid
+    Ns = np.array([24 * Z for _, Z, _ in codes])
+    Nf = np.array([Ns[c] if 0 <= c < 3 else 16 for c in cid])
+    off = np.zeros(F, np.int64)
+    off[1:] = np.cumsum(Nf)[:-1]
+    total = int(Nf.sum())
+    llr = np.zeros(total, np.float32)
+    per = {}
+    for c in range(3):
+        idx = np.flatnonzero(cid == c)
+        _, Z, h = codes[c]
+        _, _, l = oracle.llr_frames(h, Z, len(idx), 2.5, 40 + c)
+        for k, f in enumerate(idx):
+            llr[off[f]:off[f] + Ns[c]] = l[k]
+        per[c] = (idx, l)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    bits = torch.full((total,), 7, dtype=torch.uint8, device=DEV)
+    iters = torch.full((F,), -5, dtype=torch.int32, device=DEV)
+    bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=6, alpha=0.75, early_term=True,
+                                          bits=bits, iters=iters)
+    torch.cuda.synchronize()
+    bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+    for c, (idx, l) in per.items():
+        _, Z, h = codes[c]
+        wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+        for k, f in enumerate(idx):
+            s = slice(off[f], off[f] + Ns[c])
+            assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], (c, f)
+    bad = np.flatnonzero((cid < 0) | (cid >= 3))
+    assert len(bad) > 0
+    for f in bad:
+        assert iters[f] == -5 and np.all(bits[off[f]:off[f] + 16] == 7)
