@@ -83,6 +83,22 @@ __device__ __forceinline__ int gather_b(int i, int e, int r, int rbn_b, int rbw_
     return ((r >= Z - kShift[i][e]) ? rbw_b : rbn_b) + (kCol[i][e] * Z + kShift[i][e]) * FWP * 4;
 }
 
+// XOR of the bit patterns of v[0..D): two operands per v_bitop3_b32 (truth
+// table 0x96 = a ^ b ^ c) instead of one per v_xor_b32
+__device__ __forceinline__ u32 bits_of(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ u32 bits_of(u32 v) { return v; }
+template <int D, class T>
+__device__ __forceinline__ u32 xor_bits(const T *v)
+{
+    u32 p = bits_of(v[0]);
+#pragma unroll
+    for (int e = 1; e + 1 < D; e += 2)
+        p = __builtin_amdgcn_bitop3_b32(p, bits_of(v[e]), bits_of(v[e + 1]), 0x96);
+    if constexpr (D % 2 == 0)
+        p ^= bits_of(v[D - 1]);
+    return p;
+}
+
 __device__ __forceinline__ int hard_bit(float v) { return v > 0.0f ? 0 : 1; }
 
 __device__ __forceinline__ float ldb(const float *Ls, int b) { return *(const float *)((const char *)Ls + b); }
@@ -169,16 +185,14 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
 #pragma unroll
                 for (int e = 0; e < d; ++e)
                     Q[e] = ldb(Ls, gather_b(i, e, rr, rbn, rbw) + k * 4) - R[k][eo + e];
-                u32 px = 0;
                 float m1 = __builtin_inff(), m2 = __builtin_inff();
 #pragma unroll
                 for (int e = 0; e < d; ++e) {
                     const float a = __builtin_fabsf(Q[e]);
                     m2 = __builtin_amdgcn_fmed3f(a, m1, m2);
                     m1 = __builtin_amdgcn_fmed3f(a, m1, -3.402823466e38f);
-                    px ^= __float_as_uint(Q[e]);
                 }
-                const u32 par = px & 0x80000000u;
+                const u32 par = xor_bits<d>(Q) & 0x80000000u;
 #if LDPC_PATH == 0
                 const float n1 = alpha * m1, n2 = alpha * m2;
 #else

@@ -81,6 +81,20 @@ __device__ __forceinline__ void stb(u32 *Ls, int b, u32 v) { *(u32 *)((char *)Ls
 
 // hard decisions of a pair (bit 0: frame 2p, bit 16: frame 2p+1): 1 where
 // the value is <= 0, i.e. where its bits as int16 are <= 0 (no -0 occurs)
+// XOR of v[0..D): two operands per v_bitop3_b32 (truth table 0x96 =
+// a ^ b ^ c) instead of one per v_xor_b32
+template <int D>
+__device__ __forceinline__ u32 xor_bits(const u32 *v)
+{
+    u32 p = v[0];
+#pragma unroll
+    for (int e = 1; e + 1 < D; e += 2)
+        p = __builtin_amdgcn_bitop3_b32(p, v[e], v[e + 1], 0x96);
+    if constexpr (D % 2 == 0)
+        p ^= v[D - 1];
+    return p;
+}
+
 __device__ __forceinline__ u32 hard_bits(u32 x)
 {
     const u2 one = {1, 1};
@@ -185,15 +199,13 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
                     Q[e] = W(H(ldb(Ls, ix[e])) - H(R[eo + e]));
                 }
                 u2 m1 = {0x7fff, 0x7fff}, m2 = m1;
-                u32 px = 0;
 #pragma unroll
                 for (int e = 0; e < d; ++e) {
                     const u2 a = V(Q[e] & 0x7fff7fffu);
                     m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, a));
                     m1 = __builtin_elementwise_min(m1, a);
-                    px ^= Q[e];
                 }
-                const u32 par = px & 0x80008000u;
+                const u32 par = xor_bits<d>(Q) & 0x80008000u;
                 const u2 cap = {0x57f0, 0x57f0};   // 127.0 in FP16
                 const u32 c1 = W(__builtin_elementwise_min(m1, cap)), c2 = W(__builtin_elementwise_min(m2, cap));
                 u32 n1, n2;
