@@ -185,7 +185,8 @@ def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
                 res[key]["alu_frac"] = round(tops / PEAK_VALU_TOPS, 4)
     return {"workload": f"114 WiMAX-shaped synthetic codes (rate classes 1/2 2/3A 2/3B 3/4A 3/4B 5/6, "
                         f"Z=24..96, N=576..2304), {frames} frames with uniform code ids in one persistent "
-                        f"launch, Eb/N0={EBN0_DB} dB, FP32 NMS alpha={ALPHA} / int8 OMS offset={OFFSET}, "
+                        f"launch, Eb/N0={EBN0_DB} dB, FP32 NMS alpha={ALPHA} / int8 OMS offset={OFFSET} (two frames "
+                        f"per lane in packed FP16), "
                         f"{ITERS} iterations (fixed; _et: early termination)",
             "info_bits": kbits, "layouts": layouts, **res}
 

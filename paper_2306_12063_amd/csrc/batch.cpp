@@ -26,6 +26,7 @@ struct ldpc_codeset {
     std::vector<int> cls;              // class of each code
     std::vector<int> class_rep;        // a code of each class
     int cmb = 0, cd = 0;               // largest block-row count and degree
+    bool h2 = false;                   // fixed point with two frames per lane in packed FP16
     // per arithmetic path (0 FP32, 1 fixed point): layout and device tables
     int threads[2] = {256, 256};       // workgroup size of the persistent kernel
     int gdiv[2] = {1, 1};              // frames per item = floor(threads / Z) / gdiv (at most 64)
@@ -65,8 +66,23 @@ std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 {
     std::ostringstream o;
     const int nclass = (int)cs.class_rep.size();
+    // edges per thread (one message register each) of the largest class
+    int max_edges = 0;
+    for (int c = 0; c < nclass; ++c) {
+        const Sched &s = cs.sc[cs.class_rep[c]];
+        int e = 0;
+        for (int i = 0; i < s.Mb; ++i)
+            e += s.deg[i];
+        max_edges = std::max(max_edges, e);
+    }
+    // three waves per SIMD: measured on the 114-code WiMAX-shaped set
+    // (up to 102 edges per class), where it holds with a few spilled
+    // registers and makes the packed fixed-point batch 1.3x faster
+    const int waves = max_edges <= 112 ? 3 : 0;
+    o << "#define LDPC_WAVES_HINT " << waves << "\n";
     o << "#define LDPC_THREADS " << cs.threads[path] << "\n#define LDPC_LDS " << cs.lds_elems[path]
-      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n#define LDPC_NCLASS " << nclass
+      << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode
+      << "\n#define LDPC_H2 " << (path == 1 && cs.h2 ? 1 : 0) << "\n#define LDPC_NCLASS " << nclass
       << "\n#define LDPC_CMB " << cs.cmb << "\n#define LDPC_CD " << cs.cd << "\n";
     o << "__device__ constexpr int kMBc[" << nclass << "] = {";
     for (int c = 0; c < nclass; ++c)
@@ -91,24 +107,27 @@ std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 extern const char kJitBatchSource[];
 
 // (Re)builds a path's device tables for a layout: workgroups of `threads`
-// threads, floor(threads / Z) / gdiv frames per work item (at most 64).
+// threads, floor(threads / Z) / gdiv lane groups per work item (at most 64),
+// each holding one frame, or two on the packed-FP16 fixed-point path.
 int build_tables(ldpc_codeset *cs, int path, int threads, int gdiv)
 {
     const int n = cs->ncodes;
+    const int per_group = (path == 1 && cs->h2) ? 2 : 1;
     std::vector<CodeRec> rec(n);
     std::vector<int> etab, G(n);
     size_t lds = 0;
     for (int c = 0; c < n; ++c) {
         const Sched &s = cs->sc[c];
-        G[c] = std::max(1, std::min(64, threads / s.Z) / gdiv);
-        // fewer frames per item where the posteriors (one column block of
+        int groups = std::max(1, std::min(64, threads / s.Z) / gdiv);
+        // fewer groups per item where the posteriors (one column block of
         // padding included) would not fit the LDS budget
-        while (G[c] > 1 && (size_t)(s.N + s.Z) * fwp_for(G[c]) * 4 > (size_t)kLdsBudget)
-            --G[c];
-        const int FWp = fwp_for(G[c]);
+        while (groups > 1 && (size_t)(s.N + s.Z) * fwp_for(groups) * 4 > (size_t)kLdsBudget)
+            --groups;
+        const int FWp = fwp_for(groups);
         if ((size_t)(s.N + s.Z) * FWp * 4 > (size_t)kLdsBudget)
             return fail(LDPC_ERANGE, "code %d (N=%d) does not fit the batched kernel's LDS budget", c, s.N);
         lds = std::max(lds, (size_t)(s.N + s.Z) * FWp);
+        G[c] = groups * per_group;   // frames per work item
         rec[c] = CodeRec{s.Z, s.N, cs->cls[c], G[c], FWp, (int)(etab.size() / 2), 0, 0};
         for (int i = 0; i < cs->cmb; ++i)
             for (int e = 0; e < cs->cd; ++e) {
@@ -176,6 +195,14 @@ int codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, cons
             delete cs;
             return fail(LDPC_ERANGE, "code %d: Z=%d exceeds the batched kernel's workgroup", c, Z[c]);
         }
+    }
+    // two frames per lane in packed FP16 on the fixed-point path when every
+    // code allows it (LDPC_BATCH_H2=0 in the environment at creation turns it off)
+    {
+        const char *hv = getenv("LDPC_BATCH_H2");
+        cs->h2 = !(hv && hv[0] == '0');
+        for (int c = 0; c < n && cs->h2; ++c)
+            cs->h2 = h2_eligible(cs->sc[c]);
     }
     if (hipGetDevice(&cs->device) != hipSuccess) {
         delete cs;

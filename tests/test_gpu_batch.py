@@ -176,7 +176,8 @@ def test_batch_autotune_keeps_parity():
             assert np.array_equal(iters[idx], wi)
 
 
-def test_batch_grouping_one_dominant_code():
+@pytest.mark.parametrize("path", ["f32", "i8"])
+def test_batch_grouping_one_dominant_code(path):
     # Frames of a batch are grouped by code in per-workgroup LDS counts with
     # one global count per code and workgroup: here most of 9000 frames (three
     # such workgroups) share one code, some carry invalid code ids (their
@@ -205,13 +206,20 @@ def test_batch_grouping_one_dominant_code():
     d = lambda x: torch.from_numpy(x).to(DEV)
     bits = torch.full((total,), 7, dtype=torch.uint8, device=DEV)
     iters = torch.full((F,), -5, dtype=torch.int32, device=DEV)
-    bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=6, alpha=0.75, early_term=True,
-                                          bits=bits, iters=iters)
+    if path == "f32":
+        bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=6, alpha=0.75, early_term=True,
+                                              bits=bits, iters=iters)
+    else:
+        bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(oracle.quantize_i8(llr)), max_iter=6, offset=1,
+                                             early_term=True, bits=bits, iters=iters)
     torch.cuda.synchronize()
     bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
     for c, (idx, l) in per.items():
         _, Z, h = codes[c]
-        wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+        if path == "f32":
+            wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+        else:
+            wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=6, offset=1, early_term=True)
         for k, f in enumerate(idx):
             s = slice(off[f], off[f] + Ns[c])
             assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], (c, f)
@@ -219,3 +227,32 @@ def test_batch_grouping_one_dominant_code():
     assert len(bad) > 0
     for f in bad:
         assert iters[f] == -5 and np.all(bits[off[f]:off[f] + 16] == 7)
+
+
+@pytest.mark.parametrize("packed", [True, False])
+@pytest.mark.parametrize("wq", [0, 12])
+def test_batch_i8_forms(monkeypatch, packed, wq):
+    # the fixed-point batch with two frames per lane in packed FP16 (default
+    # for these codes, column weight <= 15) and, with LDPC_BATCH_H2=0 at
+    # code-set creation, one frame per lane (the form used for codes of
+    # larger column weight); offset (wq = 0) and weight wq/16 magnitudes
+    if not packed:
+        monkeypatch.setenv("LDPC_BATCH_H2", "0")
+    all_codes = synth.wimax_code_set()
+    codes = [all_codes[k] for k in range(3, len(all_codes), 9)]
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    F = 150
+    cid, off, llr, total, per = _ragged(codes, F, 2.0, 23)
+    q = oracle.quantize_i8(llr)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    for et in (True, False):
+        bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(q), max_iter=7, offset=1, wq=wq, early_term=et)
+        torch.cuda.synchronize()
+        bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+        for c, (idx, l) in per.items():
+            _, Z, h = codes[c]
+            wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=7, offset=1, wq=wq,
+                                             early_term=et)
+            for k, f in enumerate(idx):
+                s = slice(off[f], off[f] + 24 * Z)
+                assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k]
