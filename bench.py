@@ -232,7 +232,7 @@ def main():
     if not args.no_autotune:
         for c in cases:
             cfg = P.ldpc_autotune_decode(c["hbm"], Z, path=c["path"], max_iter=ITERS, F=min(F, 16384))
-            layouts[f"{c['path']} {c['rate']}"] = {k: cfg[k] for k in ("G", "KF", "threads", "hoist", "h2")}
+            layouts[f"{c['path']} {c['rate']}"] = {k: cfg[k] for k in ("G", "KF", "threads", "hoist", "h2", "waves")}
     torch.cuda.synchronize()
 
     def launch(c):

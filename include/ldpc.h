@@ -170,16 +170,19 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
  * workgroup, frames per thread, and how many block rows keep their gather
  * addresses in registers across iterations -- on F zero-valued frames at max_iter fixed
  * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
- * this code in this process (until ldpc_cache_clear). out[5] receives
- * {G, KF, FWp, threads, hoisted block rows, packed FP16} of the winner and
- * *ms its time per launch. On the fixed-point path, for codes whose values
- * fit FP16 exactly (column weight <= 15), layouts that decode two frames per
- * lane in packed FP16 are candidates too (then G counts frame pairs).
+ * this code in this process (until ldpc_cache_clear). out[7] receives
+ * {G, KF, FWp, threads, hoisted block rows, packed FP16, waves} of the
+ * winner and *ms its time per launch. On the fixed-point path, for codes
+ * whose values fit FP16 exactly (column weight <= 15), layouts that decode
+ * two frames per lane in packed FP16 are candidates too (then G counts frame
+ * pairs). A layout whose kernel needs more than 128 VGPRs per lane is also
+ * timed compiled for one more wave per SIMD (waves = 3 above 168 VGPRs,
+ * else 4), accepting at most 128 bytes of spilled registers per lane.
  * Synchronises `stream`; allocates and frees temporary device buffers.
  * LDPC_ERANGE if run-time specialisation is disabled (LDPC_JIT=0).
  */
 int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
-                         int32_t out[6], float *ms, void *stream);
+                         int32_t out[7], float *ms, void *stream);
 
 /*
  * Learned normalised min-sum (training). Weights w[T][Mb][Nb] (device f32)

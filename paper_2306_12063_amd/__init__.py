@@ -363,18 +363,18 @@ def ldpc_decode_q16(hbm, Z, llr, max_iter=10, wq=12, wrap=True, early_term=True,
 
 def ldpc_autotune_decode(hbm, Z, path="f32", max_iter=10, F=16384, stream=None):
     """Times candidate decode layouts for this code and keeps the fastest.
-    Returns dict(G, KF, FWp, threads, hoist, h2, ms); h2 = 1: two frames per
-    lane in packed FP16 (fixed point), G frame pairs per workgroup."""
+    Returns dict(G, KF, FWp, threads, hoist, h2, waves, ms); h2 = 1: two
+    frames per lane in packed FP16 (fixed point), G frame pairs per
+    workgroup; waves: occupancy target the kernel was compiled for (0: none)."""
     h = _hbm(hbm)
-    out = np.zeros(6, np.int32)
+    out = np.zeros(7, np.int32)
     ms = np.zeros(1, np.float32)
     p = {"f32": 0, "i8": 1}[path]
     _check(lib().ldpc_autotune_decode(_hptr(h), h.shape[0], h.shape[1], Z, p, int(max_iter), int(F),
                                       out.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p),
                                       _stream(stream)), "ldpc_autotune_decode")
     return dict(G=int(out[0]), KF=int(out[1]), FWp=int(out[2]), threads=int(out[3]), hoist=int(out[4]),
-                h2=int(out[5]),
-                ms=float(ms[0]))
+                h2=int(out[5]), waves=int(out[6]), ms=float(ms[0]))
 
 
 def ldpc_quantize_i8(llr, scale=4.0, out=None, stream=None):

@@ -45,7 +45,7 @@ std::string prelude(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
       << "\n#define LDPC_N " << sc.N << "\n#define LDPC_MAXD " << sc.dmax << "\n#define LDPC_G " << lc.G
       << "\n#define LDPC_KF " << lc.KF << "\n#define LDPC_FWP " << lc.FWp << "\n#define LDPC_THREADS " << lc.threads
       << "\n#define LDPC_PATH " << path << "\n#define LDPC_MODE " << mode << "\n#define LDPC_HOIST " << lc.hoist
-      << "\n";
+      << "\n#define LDPC_WAVES_HINT " << lc.waves << "\n";
     o << "__device__ constexpr int kDeg[" << sc.Mb << "] = {";
     for (int i = 0; i < sc.Mb; ++i)
         o << sc.deg[i] << (i + 1 < sc.Mb ? "," : "};\n");
@@ -381,7 +381,7 @@ DecodeLaunch jit_default_launch(const Sched &sc, int path)
     return single_frame_launch(sc);
 }
 
-int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes)
+int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes, int *vgprs)
 {
     hipFunction_t fn;
     int rc = get_decode_function(sc, lc, path, mode, &fn);
@@ -391,6 +391,11 @@ int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mo
     if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn) != hipSuccess)
         return fail(LDPC_EDEVICE, "hipFuncGetAttribute failed");
     *bytes = (size_t)v;
+    if (vgprs) {
+        if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn) != hipSuccess)
+            return fail(LDPC_EDEVICE, "hipFuncGetAttribute failed");
+        *vgprs = v;
+    }
     return LDPC_OK;
 }
 

@@ -106,7 +106,15 @@ __device__ __forceinline__ float norm_mag(float w, float m)
     return __builtin_fminf(127.0f, __builtin_floorf((w * m + 8.0f) * 0.0625f));
 }
 
-extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
+// Occupancy target chosen by the layout tuner (waves per SIMD; 0: the
+// compiler's choice).
+#if LDPC_WAVES_HINT
+#define LDPC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LDPC_WAVES_HINT)))
+#else
+#define LDPC_OCCUPANCY
+#endif
+
+extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_KERNEL(
     const signed char *__restrict__ llr, const i64 *__restrict__ fidx, const i64 Fmax, const int max_iter,
     const float alpha, const int offset, const int wq, const int et, const u8 *__restrict__ wt,
     u8 *__restrict__ bits, short *__restrict__ post, int *__restrict__ iters, u8 *__restrict__ okv,

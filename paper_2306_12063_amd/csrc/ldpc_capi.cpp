@@ -442,7 +442,7 @@ int ldpc_decode_flood_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t
 }
 
 int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, int max_iter, int64_t F,
-                         int32_t out[6], float *ms, void *stream)
+                         int32_t out[7], float *ms, void *stream)
 {
     clear_error();
     Sched sc;
@@ -466,6 +466,7 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
     out[3] = best.threads;
     out[4] = best.hoist;
     out[5] = best.h2;
+    out[6] = best.waves;
     return LDPC_OK;
 }
 

@@ -57,6 +57,7 @@ struct DecodeLaunch {
     size_t lds;  // LDS bytes of the posteriors
     int hoist = 0;  // specialised kernels: block rows whose gather addresses stay in registers
     int h2 = 0;     // fixed point with two frames per lane in packed FP16 (G = frame pairs, FW = 2G)
+    int waves = 0;  // specialised kernels: occupancy target in waves per SIMD (0: the compiler's choice)
 };
 
 // Largest column weight (block rows with an edge in a block column).
@@ -102,8 +103,10 @@ int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t 
 // addresses kept in registers when they fit beside the messages.
 DecodeLaunch jit_default_launch(const Sched &sc, int path);
 // Bytes of per-lane scratch the specialised decode kernel for this layout
-// needs (register spills); compiles the variant if necessary.
-int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes);
+// needs (register spills) and its VGPRs per lane; compiles the variant if
+// necessary.
+int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mode, size_t *bytes,
+                       int *vgprs = nullptr);
 // Flooding schedule (jit_flood.hip): layout and launch.
 DecodeLaunch flood_launch(const Sched &sc);
 int launch_jit_flood(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr, int64_t F,

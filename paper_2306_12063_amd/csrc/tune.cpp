@@ -1,9 +1,11 @@
 // Decode-layout autotuner. For one code and arithmetic path it times the
 // run-time specialised kernel over candidate layouts -- frame groups per
-// workgroup (G), frames per thread (KF) and whether gather addresses stay in
-// registers across iterations -- and keeps the fastest for later calls on
-// that code. The layouts trade registers and LDS per frame against waves
-// per SIMD, which is hard to predict, so they are measured.
+// workgroup (G), frames per thread (KF), whether gather addresses stay in
+// registers across iterations, two frames per lane in packed FP16 (fixed
+// point), and an occupancy target for the register allocator -- and keeps
+// the fastest for later calls on that code. The layouts trade registers and
+// LDS per frame against waves per SIMD, which is hard to predict, so they
+// are measured.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -34,7 +36,8 @@ std::string tune_key(const Sched &sc, int path)
 
 // Candidate layouts: workgroups of at most 256 threads whose lanes are at
 // least 85% busy, one or two frames per thread, and the number of block rows
-// whose gather addresses stay in registers (all, three quarters, half, none).
+// whose gather addresses stay in registers (all, three quarters, half, a
+// quarter, none).
 // A thread keeps KF messages per edge of its rows in VGPRs, plus an address
 // per hoisted edge; the registers decide how many waves share a SIMD, which
 // is hard to predict, so the candidates are compiled and timed, and those
@@ -43,7 +46,7 @@ std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
 {
     std::vector<DecodeLaunch> out;
     const int per_row = sc.E / sc.Z;
-    const int hoists[4] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, 0};
+    const int hoists[5] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, sc.Mb / 4, 0};
     // fixed point: two frames per lane in packed FP16 where the values fit
     if (path == 1 && h2_eligible(sc)) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
@@ -126,42 +129,59 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         rc = fail(LDPC_EDEVICE, "autotune: HIP setup failed");
         goto done;
     }
-    for (const DecodeLaunch &lc : candidates(sc, eb, path)) {
-        size_t scratch = 0;
-        if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch)))
-            goto done;
-        if (scratch > 0) {
-            if (log)
-                fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d spills %zu bytes, skipped\n", lc.G, lc.KF,
-                        lc.hoist, scratch);
-            continue;   // spills registers
-        }
-        // the first launch warms the caches
-        rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
-                               (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
-        if (rc)
-            goto done;
-        const int reps = 3;
-        hipEventRecord(e0, stream);
-        for (int k = 0; k < reps && rc == LDPC_OK; ++k)
+    {
+        // candidates, then for each one whose kernel holds more than 128
+        // VGPRs per lane the same layout compiled for one more wave per SIMD
+        // (a hint to the register allocator; a few spilled registers are
+        // accepted there, the timing decides)
+        std::vector<DecodeLaunch> work = candidates(sc, eb, path);
+        for (size_t w = 0; w < work.size(); ++w) {
+            const DecodeLaunch lc = work[w];
+            size_t scratch = 0;
+            int vgprs = 0;
+            if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch, &vgprs)))
+                goto done;
+            const size_t allowed = lc.waves ? 128 : 0;
+            if (scratch > allowed) {
+                if (log)
+                    fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d waves %d spills %zu bytes, skipped\n", lc.G,
+                            lc.KF, lc.hoist, lc.waves, scratch);
+                continue;
+            }
+            if (lc.waves == 0 && vgprs > 128) {
+                DecodeLaunch v = lc;
+                v.waves = vgprs > 168 ? 3 : 4;
+                work.push_back(v);
+            }
+            // the first launch warms the caches
             rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
                                    (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
-        hipEventRecord(e1, stream);
-        if (rc)
-            goto done;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(LDPC_EDEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
-            goto done;
-        }
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        if (log)
-            fprintf(stderr, "ldpc autotune: path %d Z %d Mb %d  G %d KF %d threads %d hoisted rows %d  %.4f ms\n", path,
-                    sc.Z, sc.Mb, lc.G, lc.KF, lc.threads, lc.hoist, ms);
-        if (ms < best_t) {
-            best_t = ms;
-            best_lc = lc;
+            if (rc)
+                goto done;
+            const int reps = 3;
+            hipEventRecord(e0, stream);
+            for (int k = 0; k < reps && rc == LDPC_OK; ++k)
+                rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
+                                       (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
+            hipEventRecord(e1, stream);
+            if (rc)
+                goto done;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(LDPC_EDEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
+                goto done;
+            }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (log)
+                fprintf(stderr,
+                        "ldpc autotune: path %d Z %d Mb %d  G %d KF %d threads %d hoisted rows %d h2 %d waves %d "
+                        "vgprs %d scratch %zu  %.4f ms\n",
+                        path, sc.Z, sc.Mb, lc.G, lc.KF, lc.threads, lc.hoist, lc.h2, lc.waves, vgprs, scratch, ms);
+            if (ms < best_t) {
+                best_t = ms;
+                best_lc = lc;
+            }
         }
     }
     if (best_lc.G < 1) {
