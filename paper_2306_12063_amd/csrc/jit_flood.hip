@@ -100,6 +100,14 @@ __device__ __forceinline__ u32 xor_bits(const T *v)
 }
 
 __device__ __forceinline__ int hard_bit(float v) { return v > 0.0f ? 0 : 1; }
+// Hard decision as bit 31 of a word: bits(v) - 1 has bit 31 set exactly
+// where v <= 0 (+0 -> 0xffffffff, negative values keep their sign bit,
+// positive ones lose nothing). Posteriors are never -0: the load maps -0 to
+// +0, and in round-to-nearest a sum or difference of values that are not -0
+// is not -0. The parity of a row's hard decisions is then bit 31 of the XOR
+// of these words, taken three operands per v_bitop3_b32.
+__device__ __forceinline__ u32 hb_word(float v) { return __float_as_uint(v) - 1u; }
+
 
 __device__ __forceinline__ float ldb(const float *Ls, int b) { return *(const float *)((const char *)Ls + b); }
 
@@ -230,18 +238,22 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
             for (int k = 0; k < KF; ++k) {
                 if (!act[k])
                     continue;
-                int bad = 0;
+                u32 bad = 0, hw = 0;
 #pragma unroll
                 for (int e = 0; e < d; ++e) {
                     const int a = gather_b(i, e, rr, rbn, rbw) + k * 4;
                     const float base = first_in_column(i, kCol[i][e]) ? ldb(Ls, a + ZOFF * 4) : ldb(Ls, a);
                     const float v = base + R[k][eo + e];
                     stb(Ls, a, v);
-                    if (i == MB - 1)
-                        bad ^= hard_bit(v);
+                    if (i == MB - 1) {   // row parity of the hard decisions, two edges at a time
+                        if (e & 1)
+                            bad = __builtin_amdgcn_bitop3_b32(bad, hw, hb_word(v), 0x96);
+                        else
+                            hw = hb_word(v);
+                    }
                 }
                 if (i == MB - 1)
-                    lastbad[k] = bad;
+                    lastbad[k] = (int)((d & 1 ? bad ^ hw : bad) >> 31);
             }
             __syncthreads();
         });
@@ -260,11 +272,11 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
                 for (int k = 0; k < KF; ++k) {
                     if (!act[k])
                         continue;
-                    int p = 0;
+                    u32 w[kDeg[i]];
 #pragma unroll
                     for (int e = 0; e < kDeg[i]; ++e)
-                        p ^= hard_bit(ldb(Ls, gather_b(i, e, rr, rbn, rbw) + k * 4));
-                    bad[k] |= p;
+                        w[e] = hb_word(ldb(Ls, gather_b(i, e, rr, rbn, rbw) + k * 4));
+                    bad[k] |= (int)(xor_bits<kDeg[i]>(w) >> 31);
                 }
             });
 #pragma unroll

@@ -95,10 +95,16 @@ __device__ __forceinline__ u32 xor_bits(const u32 *v)
     return p;
 }
 
-__device__ __forceinline__ u32 hard_bits(u32 x)
+// Hard decisions of both halves as bits 15 and 31: (x - 1) on each 16-bit
+// lane has its top bit set exactly where the FP16 value is <= 0 (posteriors
+// are never -0: the channel values are converted from integers, and in
+// round-to-nearest a sum or difference of values that are not -0 is not
+// -0), so a row's two parities are bits 15 and 31 of the XOR of these
+// words, taken three operands per v_bitop3_b32.
+__device__ __forceinline__ u32 hb_word2(u32 x)
 {
     const u2 one = {1, 1};
-    return W((V(x) - one) >> (u2){15, 15});
+    return W(V(x) - one);
 }
 
 __device__ __forceinline__ float norm_mag(float w, float m)
@@ -237,7 +243,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                 u32 n2p = n2 | par;
                 u32 dlt = W(V(n1 | par) - V(n2p));
                 asm volatile("" : "+v"(n2p), "+v"(dlt));
-                u32 bad = 0;
+                u32 bad = 0, hw = 0;
 #pragma unroll
                 for (int e = 0; e < d; ++e) {
                     const u2 a = V(Q[e] & 0x7fff7fffu);
@@ -247,11 +253,15 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                     R[eo + e] = rv;
                     const u32 lv = W(H(Q[e]) + H(rv));
                     stb(Ls, ix[e], lv);
-                    if (i == MB - 1)
-                        bad ^= hard_bits(lv);
+                    if (i == MB - 1) {   // row parities of the hard decisions, two edges at a time
+                        if (e & 1)
+                            bad = __builtin_amdgcn_bitop3_b32(bad, hw, hb_word2(lv), 0x96);
+                        else
+                            hw = hb_word2(lv);
+                    }
                 }
                 if (i == MB - 1)
-                    lastbad = bad;
+                    lastbad = (d & 1 ? bad ^ hw : bad) & 0x80008000u;
             }
             __syncthreads();
         });
@@ -264,15 +274,15 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                     if constexpr (i >= LDPC_HOIST)
                         asm volatile("" : "+v"(rr));
                     const int rbw = (rr * FWP + g) * 4, rbn = rbw + PAD * 4;
-                    u32 p = 0;
+                    u32 w[kDeg[i]];
 #pragma unroll
                     for (int e = 0; e < kDeg[i]; ++e)
-                        p ^= hard_bits(ldb(Ls, gather_b(i, e, rr, rbn, rbw)));
-                    bad |= p;
+                        w[e] = hb_word2(ldb(Ls, gather_b(i, e, rr, rbn, rbw)));
+                    bad |= xor_bits<kDeg[i]>(w) & 0x80008000u;
                 });
-                if (act[0] && (bad & 1u))
+                if (act[0] && (bad & 0x8000u))
                     unsat[2 * g] = 1;
-                if (act[1] && (bad & 0x10000u))
+                if (act[1] && (bad & 0x80000000u))
                     unsat[2 * g + 1] = 1;
             }
             __syncthreads();
