@@ -205,14 +205,17 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
  *   with the same arguments and dloss (device f32 [T], the gradient of the
  *   objective with respect to each loss[t]) computes grad_w (device f32
  *   [T][Mb][Nb], overwritten). Entries of w at zero blocks (-1 in H_bm) get a
- *   zero gradient. Iterations are recomputed from their checkpoints.
+ *   zero gradient. Iterations are recomputed from their checkpoints. The last
+ *   part of ckpt (past the checkpoints and loss terms) receives each
+ *   workgroup's partial gradients, which a second kernel sums in a fixed
+ *   order, so grad_w is the same on every run.
  * Both need run-time specialisation (LDPC_ERANGE if LDPC_JIT=0).
  */
 size_t ldpc_nms_ckpt_bytes(const int16_t *hbm, int Mb, int Nb, int Z, int64_t F, int T);
 int ldpc_nms_fwd(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, const uint8_t *cw, int64_t F, int T,
                  const float *w, void *ckpt, size_t ckpt_bytes, float *loss, float *post, void *stream);
 int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, int64_t F, int T, const float *w,
-                 const void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream);
+                 void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream);
 
 /*
  * Seeded information bits from Philox4x32-10 (Salmon et al., SC'11):

@@ -442,9 +442,19 @@ DecodeLaunch plan_nms(const Sched &sc)
     return best;
 }
 
-size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T)
+// Checkpoint buffer: per iteration and frame L and the compressed row state,
+// then the per-frame loss terms, then the adjoint's per-workgroup partial
+// weight gradients.
+static size_t nms_partial_offset(const Sched &sc, int64_t F, int T)
 {
     return (size_t)T * (size_t)F * ((size_t)sc.N + 3 * (size_t)sc.M) + (size_t)T * (size_t)F;
+}
+
+size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T)
+{
+    const DecodeLaunch lc = plan_nms(sc);
+    const size_t nwg = lc.G < 1 ? 0 : (size_t)((F + lc.G - 1) / lc.G);
+    return nms_partial_offset(sc, F, T) + nwg * (size_t)T * (size_t)sc.Mb * (size_t)sc.Nb;
 }
 
 int launch_nms_fwd(const Sched &sc, const float *llr, const uint8_t *cw, int64_t F, int T, const float *w,
@@ -468,24 +478,25 @@ int launch_nms_fwd(const Sched &sc, const float *llr, const uint8_t *cw, int64_t
     return launch(red, (unsigned)T, 256, stream, a2, "nms loss");
 }
 
-int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, const float *ckpt,
+int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, float *ckpt,
                    const float *dloss, float *grad_w, hipStream_t stream)
 {
     const DecodeLaunch lc = plan_nms(sc);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the training kernels' LDS budget", sc.N);
     const std::string pre = prelude(sc, lc, 0, 1);
-    hipFunction_t bwd, zero;
+    hipFunction_t bwd, red;
     int rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_bwd", &bwd);
-    if (rc || (rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_zero", &zero)))
+    if (rc || (rc = get_function("nms", kJitNmsSource, pre, "ldpc_nms_grad_reduce", &red)))
         return rc;
-    long long nw = (long long)T * sc.Mb * sc.Nb;
-    void *az[] = {(void *)&grad_w, (void *)&nw};
-    if ((rc = launch(zero, (unsigned)((nw + 255) / 256), 256, stream, az, "nms zero")))
+    long long Fll = (long long)F, nwg = (F + lc.G - 1) / lc.G;
+    int nw = T * sc.Mb * sc.Nb;
+    float *partial = ckpt + nms_partial_offset(sc, F, T);
+    void *a[] = {(void *)&cw, (void *)&Fll, (void *)&T, (void *)&w, (void *)&ckpt, (void *)&dloss, (void *)&partial};
+    if ((rc = launch(bwd, (unsigned)nwg, lc.threads, stream, a, "nms adjoint")))
         return rc;
-    long long Fll = (long long)F;
-    void *a[] = {(void *)&cw, (void *)&Fll, (void *)&T, (void *)&w, (void *)&ckpt, (void *)&dloss, (void *)&grad_w};
-    return launch(bwd, (unsigned)((F + lc.G - 1) / lc.G), lc.threads, stream, a, "nms adjoint");
+    void *ar[] = {(void *)&partial, (void *)&nwg, (void *)&nw, (void *)&grad_w};
+    return launch(red, (unsigned)((nw + 255) / 256), 256, stream, ar, "nms gradient sum");
 }
 
 }  // namespace ldpc

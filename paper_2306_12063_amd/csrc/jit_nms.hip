@@ -12,6 +12,10 @@
 // binary cross-entropy of sigmoid(L) (the probability of bit 0, eq. 17)
 // after every iteration. Early termination is off.
 //
+// Weight gradients: each lane holds one term per weight and iteration; the
+// terms are summed across the wave (DPP), then per workgroup in LDS; each
+// workgroup stores its sums and a reduction kernel adds them up.
+//
 // Checkpoint of iteration t (taken when it starts), per frame: L (N FP32)
 // and the compressed row state (raw minima m1, m2 and sign/argmin word,
 // one triple per check row). The adjoint restores it, recomputes the
@@ -55,6 +59,27 @@ __device__ __forceinline__ int gather(int i, int e, int r, int rb)
 {
     const int base = (kCol[i][e] * Z + kShift[i][e]) * FWP;
     return rb + base - ((r >= Z - kShift[i][e]) ? ZFW : 0);
+}
+
+// Sum of v over the 64 lanes of the wave (every lane active): inclusive sums
+// within rows of 16 lanes by DPP row shifts, then row_bcast:15 and
+// row_bcast:31 carry the row totals up, leaving the total in lane 63. Lanes
+// a DPP source does not cover (row edge, rows outside the row mask) add 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                                                     0xf, false));
+}
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 __device__ __forceinline__ float softplus(float z) { return __builtin_fmaxf(z, 0.0f) + log1pf(expf(-__builtin_fabsf(z))); }
@@ -224,7 +249,7 @@ extern "C" __global__ __launch_bounds__(256) void ldpc_nms_loss_reduce(const flo
 
 extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
     const u8 *__restrict__ cw, const i64 F, const int T, const float *__restrict__ w,
-    const float *__restrict__ ckpt, const float *__restrict__ dloss, float *__restrict__ grad_w)
+    const float *__restrict__ ckpt, const float *__restrict__ dloss, float *__restrict__ partial)
 {
     __shared__ float Ls[N * FWP];
     __shared__ float gL[N * FWP];
@@ -284,6 +309,10 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
         for (int ii = 0; ii < MB; ++ii) {
             const int i = MB - 1 - ii;
             const int d = kDeg[i];
+            float gwc[MAXD];   // this lane's terms of the row's weight gradients
+#pragma unroll
+            for (int e = 0; e < MAXD; ++e)
+                gwc[e] = 0.0f;
             if (on) {
                 const float *Q = QS + edge_off(i);
                 float *gr = gR + edge_off(i);
@@ -330,7 +359,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
                     const float m = (e == a1) ? v2 : v1;
                     const float Ge = gl[e] + gr[e];
                     const float wv = w[(t * MB + i) * NB + kCol[i][e]];
-                    atomicAdd(&gw[i * NB + kCol[i][e]], Ge * sg * m);
+                    gwc[e] = Ge * sg * m;
                     const float gm = Ge * sg * wv;
                     if (e == a1)
                         gQ2 += gm;
@@ -348,22 +377,40 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
                     gr[e] = -gq;
                 }
             }
+            // one LDS atomic per wave and weight: every lane of the workgroup
+            // adds to the same weights, so summing across the wave first
+            // avoids 64-way serialised atomics on one address
+#pragma unroll
+            for (int e = 0; e < MAXD; ++e) {
+                if (e >= d)
+                    continue;
+                const float s = wave_sum(gwc[e]);
+                if ((tid & 63) == 0)
+                    atomicAdd(&gw[i * NB + kCol[i][e]], s);
+            }
             __syncthreads();
         }
-        // this iteration's weight gradient: one atomic per weight and workgroup
+        // this iteration's weight gradient of the workgroup's frames, summed
+        // over workgroups by ldpc_nms_grad_reduce (global atomics from every
+        // workgroup on the same few thousand weights would serialise)
         for (int k = tid; k < MB * NB; k += LDPC_THREADS) {
-            const float v = gw[k];
-            if (v != 0.0f)
-                atomicAdd(&grad_w[t * MB * NB + k], v);
+            partial[((i64)blockIdx.x * T + t) * (MB * NB) + k] = gw[k];
             gw[k] = 0.0f;
         }
         __syncthreads();
     }
 }
 
-extern "C" __global__ void ldpc_nms_zero(float *__restrict__ p, const i64 n)
+// grad_w[k] = sum over the adjoint's workgroups b of partial[b][k], k over
+// the T*MB*NB weights, in workgroup order (the same sum on every run).
+extern "C" __global__ void ldpc_nms_grad_reduce(const float *__restrict__ partial, const i64 nwg, const int nw,
+                                                float *__restrict__ grad_w)
 {
-    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n)
-        p[k] = 0.0f;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nw)
+        return;
+    double s = 0.0;
+    for (i64 b = 0; b < nwg; ++b)
+        s += (double)partial[b * nw + k];
+    grad_w[k] = (float)s;
 }

@@ -500,7 +500,7 @@ int ldpc_nms_fwd(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr, co
 }
 
 int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, int64_t F, int T, const float *w,
-                 const void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream)
+                 void *ckpt, size_t ckpt_bytes, const float *dloss, float *grad_w, void *stream)
 {
     clear_error();
     Sched sc;
@@ -515,7 +515,7 @@ int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, i
         return fail(LDPC_EINVAL, "checkpoint buffer too small");
     if (!jit_enabled())
         return fail(LDPC_ERANGE, "the training kernels need run-time specialisation (LDPC_JIT=0 is set)");
-    return launch_nms_bwd(sc, cw, F, T, w, (const float *)ckpt, dloss, grad_w, (hipStream_t)stream);
+    return launch_nms_bwd(sc, cw, F, T, w, (float *)ckpt, dloss, grad_w, (hipStream_t)stream);
 }
 
 int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream)

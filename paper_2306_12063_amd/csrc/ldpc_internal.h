@@ -124,7 +124,7 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
 size_t nms_ckpt_floats(const Sched &sc, int64_t F, int T);
 int launch_nms_fwd(const Sched &sc, const float *llr, const uint8_t *cw, int64_t F, int T, const float *w,
                    float *ckpt, float *loss, float *post, hipStream_t stream);
-int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, const float *ckpt,
+int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const float *w, float *ckpt,
                    const float *dloss, float *grad_w, hipStream_t stream);
 
 // Picks G/KF for a code and element size (4 for FP32, 2 for int16 posteriors).

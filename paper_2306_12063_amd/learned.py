@@ -23,23 +23,30 @@ from . import (ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_encode, ldp
 from .nms import nms_loss, quantize_weights
 
 
-def make_frames(hbm, Z, F, ebn0_db, seed, device="cuda"):
+def awgn_params(ebn0_db, rate):
+    """Per-frame noise deviation and LLR scale (FP32) for Eb/N0 values in dB."""
+    e = np.asarray(ebn0_db, dtype=np.float64)
+    s2 = 1.0 / (2.0 * rate * np.power(10.0, e / 10.0))
+    return np.sqrt(s2).astype(np.float32), (2.0 / s2).astype(np.float32)
+
+
+def make_frames(hbm, Z, F, ebn0_db, seed, device="cuda", sigma_scale=None):
     """(info, codewords, channel LLRs) of F seeded frames; ebn0_db is a
-    number or an array of per-frame values (dB)."""
+    number or an array of per-frame values (dB), or sigma_scale gives the
+    per-frame (sigma, scale) as device tensors."""
     info = ldpc_code_info(hbm, Z)
     N, K = info["N"], info["K"]
     rate = K / N
     bits = ldpc_random_bits(seed, F, K, device=device)
     cw = ldpc_encode(hbm, Z, bits)
-    if np.isscalar(ebn0_db):
+    if sigma_scale is not None:
+        llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, sigma_scale[0], sigma_scale[1])
+    elif np.isscalar(ebn0_db):
         s2 = synth.sigma2_from_ebn0(float(ebn0_db), rate)
         llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, math.sqrt(s2), 2.0 / s2)
     else:
-        e = np.asarray(ebn0_db, dtype=np.float64)
-        s2 = 1.0 / (2.0 * rate * np.power(10.0, e / 10.0))
-        sigma = torch.from_numpy(np.sqrt(s2).astype(np.float32)).to(device)
-        scale = torch.from_numpy((2.0 / s2).astype(np.float32)).to(device)
-        llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, sigma, scale)
+        sg, sc = awgn_params(ebn0_db, rate)
+        llr = ldpc_awgn_llr(seed ^ 0x5DEECE66D, cw, torch.from_numpy(sg).to(device), torch.from_numpy(sc).to(device))
     return bits, cw, llr
 
 
@@ -74,20 +81,28 @@ def train(hbm, Z, T=10, frames=1 << 20, batch=4096, lr=1e-2, ebn0_range=(1.0, 4.
     rng = np.random.default_rng(seed)
     history = []
     steps = max(1, frames // batch)
+    # every step's per-frame Eb/N0 drawn at once (the same sequence as one
+    # draw per step) and copied to the device in one transfer: a per-step
+    # copy from pageable memory would make the host wait for the GPU
+    info = ldpc_code_info(hbm, Z)
+    sg, sc = awgn_params(rng.uniform(ebn0_range[0], ebn0_range[1], (steps, batch)), info["K"] / info["N"])
+    sg, sc = torch.from_numpy(sg).to(device), torch.from_numpy(sc).to(device)
     for step in range(steps):
         if lr_final is not None:
             for gr in opt.param_groups:
                 gr["lr"] = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / steps))
-        e = rng.uniform(ebn0_range[0], ebn0_range[1], batch)
-        _, cw, llr = make_frames(hbm, Z, batch, e, seed * 1000003 + step, device)
+        _, cw, llr = make_frames(hbm, Z, batch, None, seed * 1000003 + step, device, sigma_scale=(sg[step], sc[step]))
         opt.zero_grad(set_to_none=True)
         w = p.expand(T, Mb, Nb)
         per_iter = nms_loss(w, llr, cw, hbm, Z)
         (per_iter * gam).sum().backward()
         opt.step()
-        history.append(float(per_iter.detach().sum()))
+        # kept on the device: reading it back every step would make the host
+        # wait for the GPU before it can queue the next step
+        history.append(per_iter.detach().sum())
         if log_every and (step % log_every == 0 or step == steps - 1):
-            print(f"  step {step:4d}/{steps}  loss {history[-1]:.5f}", flush=True)
+            print(f"  step {step:4d}/{steps}  loss {float(history[-1]):.5f}", flush=True)
+    history = [float(x) for x in torch.stack(history).cpu()]
     return p.detach().expand(T, Mb, Nb).contiguous(), history
 
 
