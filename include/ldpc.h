@@ -177,7 +177,7 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
  * two frames per lane in packed FP16 are candidates too (then G counts frame
  * pairs). A layout whose kernel needs more than 128 VGPRs per lane is also
  * timed compiled for one more wave per SIMD (waves = 3 above 168 VGPRs,
- * else 4); such a variant may spill at most 64 bytes of registers per lane
+ * else 4); such a variant may spill at most 32 bytes of registers per lane
  * (scratch memory, extra HBM traffic) and is kept only if it is at least 5%
  * faster than the fastest layout that does not spill.
  * Synchronises `stream`; allocates and frees temporary device buffers.

@@ -134,7 +134,7 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         // VGPRs per lane the same layout compiled for one more wave per SIMD
         // (a hint to the register allocator). Spilled registers live in
         // scratch memory and add HBM traffic, so such a variant may spill at
-        // most 64 bytes per lane and replaces the fastest spill-free layout
+        // most 32 bytes per lane and replaces the fastest spill-free layout
         // only if it is at least 5% faster.
         std::vector<DecodeLaunch> work = candidates(sc, eb, path);
         for (size_t w = 0; w < work.size(); ++w) {
@@ -143,7 +143,7 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
             int vgprs = 0;
             if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch, &vgprs)))
                 goto done;
-            const size_t allowed = lc.waves ? 64 : 0;
+            const size_t allowed = lc.waves ? 32 : 0;
             if (scratch > allowed) {
                 if (log)
                     fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d waves %d spills %zu bytes, skipped\n", lc.G,
