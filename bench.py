@@ -187,6 +187,45 @@ def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
                 tops = ALG_OPS_PER_EDGE_ITER * edges * ITERS / (ms / 1e3) / 1e12
                 res[key]["valu_tops"] = round(tops, 3)
                 res[key]["alu_frac"] = round(tops / PEAK_VALU_TOPS, 4)
+    # The fixed-iteration decodes captured once each in a HIP graph (the six
+    # stream-ordered kernels of a batched decode) and replayed; every replay
+    # must reproduce the eager result.
+    graph = {}
+    for path in ("f32", "i8"):
+        def run_g():
+            if path == "f32":
+                cs.decode_f32(d_cid, d_off, llr, max_iter=ITERS, alpha=ALPHA, early_term=False, bits=bits,
+                              iters=iters, ok=ok, work=work, want_post=False)
+            else:
+                cs.decode_i8(d_cid, d_off, q, max_iter=ITERS, offset=OFFSET, early_term=False, bits=bits,
+                             iters=iters, ok=ok, work=work, want_post=False)
+        run_g()
+        torch.cuda.synchronize()
+        ref = bits.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # warm-up on the capture stream
+            run_g()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run_g()
+        bits.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(bits, ref))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(bits, ref))
+        ms = e0.elapsed_time(e1) / steps
+        graph[path] = {"ms": round(ms, 4), "gbit_s": round(kbits / (ms / 1e3) / 1e9, 3), "replays_equal_eager": same}
+        del g
+    res["graph_replay"] = graph
     return {"workload": f"114 WiMAX-shaped synthetic codes (rate classes 1/2 2/3A 2/3B 3/4A 3/4B 5/6, "
                         f"Z=24..96, N=576..2304), {frames} frames with uniform code ids in one persistent "
                         f"launch, Eb/N0={EBN0_DB} dB, FP32 NMS alpha={ALPHA} / int8 OMS offset={OFFSET} (two frames "
