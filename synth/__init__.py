@@ -197,3 +197,24 @@ def sigma2_from_ebn0(ebn0_db: float, rate: float) -> float:
     """Noise variance for BPSK at Eb/N0 (dB) and code rate R:
     sigma^2 = 1 / (2 R 10^(Eb/N0 / 10))."""
     return 1.0 / (2.0 * rate * math.pow(10.0, ebn0_db / 10.0))
+
+
+def heavy_column_code(Mb: int, heavy: int, Z: int, seed: int) -> np.ndarray:
+    """A decodable QC base matrix of Mb x 24 blocks whose block column 0 has
+    weight `heavy` and whose other columns are lighter (5 random blocks per
+    row in columns 1..23, shifts uniform); it has no encoder structure. Used
+    to test the column-weight limit of the packed fixed-point kernels."""
+    rng = np.random.default_rng(seed)
+    h = np.full((Mb, 24), -1, np.int16)
+    for i in range(Mb):
+        cols = rng.choice(np.arange(1, 24), size=5, replace=False)
+        h[i, cols] = rng.integers(0, Z, 5)
+    h[:heavy, 0] = rng.integers(0, Z, heavy)
+    return h
+
+
+def zero_word_llr(N: int, F: int, seed: int, sigma: float = 0.9) -> np.ndarray:
+    """Channel LLRs (2y/sigma^2, FP32 [F][N]) of the all-zero word, a codeword
+    of every linear code, sent as BPSK +1 over AWGN of deviation sigma."""
+    z = std_normal(F, N, seed)
+    return (np.float32(2.0 / sigma**2) * (np.float32(1.0) + np.float32(sigma) * z)).astype(np.float32)

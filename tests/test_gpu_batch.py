@@ -256,3 +256,49 @@ def test_batch_i8_forms(monkeypatch, packed, wq):
             for k, f in enumerate(idx):
                 s = slice(off[f], off[f] + 24 * Z)
                 assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k]
+
+
+@pytest.mark.parametrize("with_heavy", [False, True])
+def test_batch_mixed_families(with_heavy):
+    # Wi-Fi-shaped Z=81 codes and WiMAX-shaped codes in one code set (four
+    # structure classes); with a code of column weight 16 added, the int8
+    # batch must leave packed FP16 for the whole set (one frame per lane).
+    codes = [("wifi 1/2", 81, synth.wifi_code("1/2", 81)), ("wifi 5/6", 81, synth.wifi_code("5/6", 81)),
+             ("wimax 2/3B", 40, synth.wimax_code("2/3B", 40))]
+    if with_heavy:
+        codes.append(("weight 16", 32, synth.heavy_column_code(16, 16, 32, 66)))
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    assert cs.info[0]["nclass"] == len(codes)
+    F = 240
+    rng = np.random.default_rng(8)
+    cid = rng.integers(0, len(codes), F).astype(np.int32)
+    Ns = np.array([24 * Z for _, Z, _ in codes])
+    off = np.zeros(F, np.int64)
+    off[1:] = np.cumsum(Ns[cid])[:-1]
+    llr = np.zeros(int(Ns[cid].sum()), np.float32)
+    per = {}
+    for c in range(len(codes)):
+        idx = np.flatnonzero(cid == c)
+        l = synth.zero_word_llr(Ns[c], len(idx), 90 + c, sigma=0.85)
+        for k, f in enumerate(idx):
+            llr[off[f]:off[f] + Ns[c]] = l[k]
+        per[c] = (idx, l)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    for path in ("f32", "i8"):
+        if path == "f32":
+            bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=8, alpha=0.75, early_term=True)
+        else:
+            bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(oracle.quantize_i8(llr)), max_iter=8, offset=1,
+                                                 early_term=True)
+        torch.cuda.synchronize()
+        bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+        for c, (idx, l) in per.items():
+            _, Z, h = codes[c]
+            if path == "f32":
+                wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=8, alpha=0.75, early_term=True)
+            else:
+                wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=8, offset=1, early_term=True)
+            for k, f in enumerate(idx):
+                s = slice(off[f], off[f] + Ns[c])
+                assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], \
+                    (path, codes[c][0], f)

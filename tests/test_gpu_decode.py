@@ -264,3 +264,28 @@ def test_precompiled_kernels_match_oracle(rate, Z, monkeypatch):
         torch.cuda.synchronize()
         assert np.array_equal(gb.cpu().numpy(), wb) and np.array_equal(gpost.cpu().numpy(), wpost)
         assert np.array_equal(gi.cpu().numpy(), wi) and np.array_equal(go.cpu().numpy(), wo)
+
+
+@pytest.mark.parametrize("Mb,heavy", [(15, 15), (16, 16)])
+def test_int8_column_weight_boundary(Mb, heavy):
+    # Column weight 15 keeps every fixed-point value below 2048 (exact in
+    # FP16: the two-frames-per-lane kernel); weight 16 must fall back to one
+    # frame per lane. Both must be bit-exact against the oracle.
+    Z = 32
+    h = synth.heavy_column_code(Mb, heavy, Z, 50 + Mb)
+    q = oracle.quantize_i8(synth.zero_word_llr(24 * Z, 37, 60 + Mb))
+    try:
+        for et in (True, False):
+            got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=12, offset=1, early_term=et)
+            torch.cuda.synchronize()
+            _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=12, offset=1, early_term=et))
+        # untuned, the weight-15 code ran two frames per lane; the tuner may
+        # choose either kernel for it, never the packed one for weight 16
+        cfg = P.ldpc_autotune_decode(h, Z, path="i8", max_iter=4, F=1024)
+        if heavy > 15:
+            assert cfg["h2"] == 0
+        got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=12, offset=1, early_term=True)
+        torch.cuda.synchronize()
+        _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=12, offset=1, early_term=True))
+    finally:
+        P.ldpc_cache_clear()
