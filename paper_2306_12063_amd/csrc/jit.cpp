@@ -181,14 +181,17 @@ int get_module(const char *tag, const char *src, const std::string &pre, hipModu
     const std::string full = pre + src;
     const std::string cpath = cache_path(full, arch);
     int rc;
-    if (!cache_read(cpath, &code)) {
+    JitKernel k;
+    const bool cached = cache_read(cpath, &code);
+    // a cached object that does not load (a damaged file) is compiled again
+    if (!cached || load(code, &k) != LDPC_OK) {
+        clear_error();
         if ((rc = rtc_compile(full, arch, &code)))
             return rc;
         cache_write(cpath, code);
+        if ((rc = load(code, &k)))
+            return rc;
     }
-    JitKernel k;
-    if ((rc = load(code, &k)))
-        return rc;
     g_cache.emplace(key, k);
     *mod = k.mod;
     return LDPC_OK;
