@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-mixed-batch", action="store_true",
                     help="skip the secondary mixed-code batch measurement (114 codes, one persistent launch)")
     ap.add_argument("--batch-frames", type=int, default=1 << 18)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the Eb/N0 sweep with early termination and the small-code record")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-plain Eb/N0 comparison (secondary record)")
     ap.add_argument("--learned-train-frames", type=int, default=1 << 21)
@@ -117,8 +119,15 @@ def cpu_baseline(cases, nframes):
             list(ex.map(fn, [ix for ix in chunks if len(ix)]))
             bits += nframes * c["K"]
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": bits / dt / 1e9, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nframes} frames per rate and path (FP32 and int8, 4 rates, Z=81), "
+            "sample": f"{model}, oracle built with gcc -O2 -ffp-contract=off; "
+                      f"{nframes} frames per rate and path (FP32 and int8, 4 rates, Z=81), "
                       f"{ITERS} fixed iterations, {dt:.1f} s wall"}
 
 
@@ -234,6 +243,79 @@ def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
             "info_bits": kbits, "layouts": layouts, **res}
 
 
+def _frames_at(P, hbm, Zc, F, ebn0, seed, dev):
+    """info, channel LLRs and their int8 quantisation for F seeded frames."""
+    import synth
+    info = P.ldpc_code_info(hbm, Zc)
+    s2 = synth.sigma2_from_ebn0(ebn0, info["K"] / info["N"])
+    bits_in = P.ldpc_random_bits(seed, F, info["K"], device=dev)
+    llr = P.ldpc_awgn_llr(seed + 1, P.ldpc_encode(hbm, Zc, bits_in), float(np.sqrt(s2)), 2.0 / s2)
+    return bits_in, llr, P.ldpc_quantize_i8(llr)
+
+
+def _decode_stats(P, torch, run, bits_in, reps):
+    """Runs the decode `run` reps times (HIP events around them) and counts
+    the last result's errors: (ms per decode, FER, mean iterations)."""
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = run()
+    e1.record()
+    bits, _, iters, ok = out
+    cnt = P.ldpc_frame_stats(bits, bits_in, iters, ok)
+    torch.cuda.synchronize()
+    c = cnt.cpu().numpy()
+    F = bits.shape[0]
+    return e0.elapsed_time(e1) / reps, c[1] / F, c[2] / F
+
+
+def et_sweep(P, torch, dev, frames):
+    """Untimed record: the Z=81 codes over Eb/N0 0..5 dB (step 0.5) with
+    early termination on (at most 10 iterations): per rate and path, the frame
+    error rate, mean iterations and decoded information Gbit/s."""
+    import synth
+    pts = [0.5 * k for k in range(11)]
+    out = {}
+    for rate in synth.WIFI_RATES:
+        h = synth.wifi_code(rate, Z)
+        K = P.ldpc_code_info(h, Z)["K"]
+        rows = {"f32": [], "i8": []}
+        for k, eb in enumerate(pts):
+            bits_in, llr, q = _frames_at(P, h, Z, frames, eb, SEED + 100 * k, dev)
+            for path in ("f32", "i8"):
+                if path == "f32":
+                    run = lambda: P.ldpc_decode_f32(h, Z, llr, max_iter=ITERS, alpha=ALPHA, early_term=True,
+                                                    want_post=False)
+                else:
+                    run = lambda: P.ldpc_decode_i8(h, Z, q, max_iter=ITERS, offset=OFFSET, early_term=True,
+                                                   want_post=False)
+                ms, fer, it = _decode_stats(P, torch, run, bits_in, 2)
+                rows[path].append({"ebn0": eb, "fer": round(float(fer), 6), "mean_iters": round(float(it), 3),
+                                   "gbit_s": round(frames * K / (ms / 1e3) / 1e9, 2)})
+        out[rate] = rows
+    return {"workload": f"Wi-Fi-shaped synthetic codes, Z={Z}, {frames} frames per point, Eb/N0 0..5 dB step "
+                        f"0.5, FP32 NMS alpha={ALPHA} and int8 OMS offset={OFFSET}, at most {ITERS} iterations "
+                        f"with early termination", "points": out}
+
+
+def small_code(P, torch, dev):
+    """Untimed record: the small Wi-Fi-shaped rate-1/2 code at Z=27 (N=648),
+    1000 frames at 2 dB, FP32 NMS with early termination (launch-bound)."""
+    import synth
+    Zs, F = 27, 1000
+    h = synth.wifi_code("1/2", Zs)
+    K = P.ldpc_code_info(h, Zs)["K"]
+    bits_in, llr, _ = _frames_at(P, h, Zs, F, EBN0_DB, SEED + 7, dev)
+    run = lambda: P.ldpc_decode_f32(h, Zs, llr, max_iter=ITERS, alpha=ALPHA, early_term=True, want_post=False)
+    ms, fer, it = _decode_stats(P, torch, run, bits_in, 20)
+    return {"workload": f"Wi-Fi-shaped synthetic rate-1/2 code, Z={Zs} (N=648), {F} frames at {EBN0_DB} dB, FP32 "
+                        f"NMS alpha={ALPHA}, at most {ITERS} iterations with early termination",
+            "ms": round(ms, 4), "gbit_s": round(F * K / (ms / 1e3) / 1e9, 3), "fer": round(float(fer), 5),
+            "mean_iters": round(float(it), 3)}
+
+
 def learned_gain(train_frames, eval_frames):
     """The metric's second part, untimed: Eb/N0 where the first-pass frame
     error rate crosses 1e-3 for plain NMS (alpha 0.75) and for the learned
@@ -256,6 +338,7 @@ def learned_gain(train_frames, eval_frames):
                         f"fresh frames (Eb/N0 uniform 1-4 dB), evaluation on {eval_frames} frames per point at "
                         f"{pts[0]}..{pts[-1]} dB step 0.1, 10 iterations with early termination",
             "train_seconds": rnd(r["train_seconds"], 2),
+            "loss_first_last": [rnd(r["loss_first"], 5), rnd(r["loss_last"], 5)],
             "ebn0_at_fer_1e3_db": {k: rnd(v["ebn0_at_fer_1e3"]) for k, v in sm.items()},
             "gain_db": {k: rnd(v["gain_db"]) for k, v in sm.items() if k != "plain_nms_f32"},
             "mean_iters_at_plain_point": {k: rnd(v["mean_iters_at_plain_point"]) for k, v in sm.items()},
@@ -374,6 +457,9 @@ def main():
     }
     if not args.no_mixed_batch:
         out["mixed_batch"] = mixed_batch(P, torch, dev, args.steps, args.batch_frames)
+    if not args.no_sweep:
+        out["et_sweep"] = et_sweep(P, torch, dev, F)
+        out["small_code"] = small_code(P, torch, dev)
     if not args.no_learned:
         out["learned"] = learned_gain(args.learned_train_frames, args.learned_eval_frames)
     if args.copy_mib > 0:

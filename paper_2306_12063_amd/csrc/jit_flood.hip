@@ -258,10 +258,22 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
             __syncthreads();
         });
         if (check) {
-            int bad[KF];
+            // a failing row of the last block row decides a frame at once;
+            // the check pass runs for the frames whose last block row is
+            // satisfied (marking a frame while another thread still reads
+            // its mark is harmless: it is unsatisfied either way)
 #pragma unroll
             for (int k = 0; k < KF; ++k)
-                bad[k] = lastbad[k];
+                if (act[k] && lastbad[k])
+                    unsat[slot0 + k] = 1;
+            __syncthreads();
+            bool need[KF];
+            int bad[KF];
+#pragma unroll
+            for (int k = 0; k < KF; ++k) {
+                need[k] = act[k] && unsat[slot0 + k] == 0;
+                bad[k] = 0;
+            }
             static_for<0, MB - 1>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 int rr = r;
@@ -270,7 +282,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
                 const int rbw = (rr * FWP + slot0) * 4, rbn = rbw + PAD * 4;
 #pragma unroll
                 for (int k = 0; k < KF; ++k) {
-                    if (!act[k])
+                    if (!need[k])
                         continue;
                     u32 w[kDeg[i]];
 #pragma unroll
@@ -281,7 +293,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
             });
 #pragma unroll
             for (int k = 0; k < KF; ++k)
-                if (act[k] && bad[k])
+                if (need[k] && bad[k])
                     unsat[slot0 + k] = 1;
             __syncthreads();
             int any = 0;

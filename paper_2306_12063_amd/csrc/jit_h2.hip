@@ -266,8 +266,18 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
             __syncthreads();
         });
         if (check) {
-            u32 bad = lastbad;
-            if (act[0] || act[1]) {
+            // a failing row of the last block row decides a frame at once;
+            // the check pass runs for the frames whose last block row is
+            // satisfied (marking a frame while another thread still reads
+            // its mark is harmless: it is unsatisfied either way)
+            if (act[0] && (lastbad & 0x8000u))
+                unsat[2 * g] = 1;
+            if (act[1] && (lastbad & 0x80000000u))
+                unsat[2 * g + 1] = 1;
+            __syncthreads();
+            const bool need0 = act[0] && unsat[2 * g] == 0, need1 = act[1] && unsat[2 * g + 1] == 0;
+            u32 bad = 0;
+            if (need0 || need1) {
                 static_for<0, MB - 1>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     int rr = r;
@@ -280,9 +290,9 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                         w[e] = hb_word2(ldb(Ls, gather_b(i, e, rr, rbn, rbw)));
                     bad |= xor_bits<kDeg[i]>(w) & 0x80008000u;
                 });
-                if (act[0] && (bad & 0x8000u))
+                if (need0 && (bad & 0x8000u))
                     unsat[2 * g] = 1;
-                if (act[1] && (bad & 0x80000000u))
+                if (need1 && (bad & 0x80000000u))
                     unsat[2 * g + 1] = 1;
             }
             __syncthreads();
