@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-mixed-batch", action="store_true",
                     help="skip the secondary mixed-code batch measurement (114 codes, one persistent launch)")
     ap.add_argument("--batch-frames", type=int, default=1 << 18)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replay timing of the mixed-code batch")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the Eb/N0 sweep with early termination and the small-code record")
     ap.add_argument("--no-learned", action="store_true",
@@ -131,7 +133,7 @@ def cpu_baseline(cases, nframes):
                       f"{ITERS} fixed iterations, {dt:.1f} s wall"}
 
 
-def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
+def mixed_batch(P, torch, dev, steps, frames, seed=SEED, graphs=True):
     """Frames of all 114 WiMAX-shaped codes (6 rate classes x Z = 24..96) in
     one persistent launch: code ids uniform, ragged lengths, Eb/N0 2 dB.
     Untimed: frame generation and the batch layout autotuner. Timed: `steps`
@@ -200,7 +202,7 @@ def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
     # stream-ordered kernels of a batched decode) and replayed; every replay
     # must reproduce the eager result.
     graph = {}
-    for path in ("f32", "i8"):
+    for path in (("f32", "i8") if graphs else ()):
         def run_g():
             if path == "f32":
                 cs.decode_f32(d_cid, d_off, llr, max_iter=ITERS, alpha=ALPHA, early_term=False, bits=bits,
@@ -234,7 +236,8 @@ def mixed_batch(P, torch, dev, steps, frames, seed=SEED):
         ms = e0.elapsed_time(e1) / steps
         graph[path] = {"ms": round(ms, 4), "gbit_s": round(kbits / (ms / 1e3) / 1e9, 3), "replays_equal_eager": same}
         del g
-    res["graph_replay"] = graph
+    if graphs:
+        res["graph_replay"] = graph
     return {"workload": f"114 WiMAX-shaped synthetic codes (rate classes 1/2 2/3A 2/3B 3/4A 3/4B 5/6, "
                         f"Z=24..96, N=576..2304), {frames} frames with uniform code ids in one persistent "
                         f"launch, Eb/N0={EBN0_DB} dB, FP32 NMS alpha={ALPHA} / int8 OMS offset={OFFSET} (two frames "
@@ -456,7 +459,7 @@ def main():
                         if k not in ("alg_ops", "hbm_bytes")} for p in per],
     }
     if not args.no_mixed_batch:
-        out["mixed_batch"] = mixed_batch(P, torch, dev, args.steps, args.batch_frames)
+        out["mixed_batch"] = mixed_batch(P, torch, dev, args.steps, args.batch_frames, graphs=not args.no_graph)
     if not args.no_sweep:
         out["et_sweep"] = et_sweep(P, torch, dev, F)
         out["small_code"] = small_code(P, torch, dev)
