@@ -352,7 +352,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(frames are independent, so a multi-GPU run would split the batch; see DESIGN.md)",
+              "(frames are independent: a multi-GPU run would give each GPU a share of the frames and add up the "
+              "error and iteration counters)",
               file=sys.stderr)
         sys.exit(2)
 
