@@ -351,7 +351,7 @@ def learned_gain(train_frames, eval_frames):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(frames are independent: a multi-GPU run would give each GPU a share of the frames and add up the "
               "error and iteration counters)",
               file=sys.stderr)
