@@ -9,7 +9,7 @@ saturating int8/int16 offset min-sum (offset 1) -- at a fixed 10 iterations
 with early termination off, as the paper times its decoders. The reported
 value is decoded information bits per second over the whole step.
 
-Prints one JSON line. `--gpus` above 1 is refused: this build runs on one GPU.
+Prints one JSON line. `--gpus` above 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import hashlib

@@ -6,7 +6,7 @@ namespace ldpc {
 
 namespace {
 
-// Shapes compiled by the build (one object each). Unused layer and edge
+// Shapes compiled into the library (one object each). Unused layer and edge
 // slots of a larger shape are skipped by uniform branches.
 struct Shape {
     int mb, maxd;

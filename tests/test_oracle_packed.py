@@ -39,7 +39,7 @@ def test_shift_group_laws():
 
 def test_fig1_shifts_congruent_modulo_word_size():
     # Z = 24, word = 8 bits: shifting by 3, 11 and 19 yields the same bytes at
-    # positions rotated by one (Fig. 1; with this build's shift direction
+    # positions rotated by one (Fig. 1; with the code's shift direction
     # out[r] = in[r + s], byte 1 of s = 3 equals byte 0 of s = 11 and byte 2
     # of s = 19)
     Z = 24
