@@ -218,3 +218,21 @@ def zero_word_llr(N: int, F: int, seed: int, sigma: float = 0.9) -> np.ndarray:
     of every linear code, sent as BPSK +1 over AWGN of deviation sigma."""
     z = std_normal(F, N, seed)
     return (np.float32(2.0 / sigma**2) * (np.float32(1.0) + np.float32(sigma) * z)).astype(np.float32)
+
+
+def limit_code(Mb: int, Nb: int, Z: int, full_row_degree: int, other_degree: int, seed: int) -> np.ndarray:
+    """An encodable base matrix at chosen sizes (the library's limits in the
+    tests): the dual-diagonal parity part of the Wi-Fi shape (h_b = 1 at rows
+    0 and M_b-1, 0 at row y), block row 0 of check degree `full_row_degree`
+    and the others of degree `other_degree`, information columns drawn
+    uniformly, shifts uniform in [0, Z-1]. Returns int16 [Mb][Nb]."""
+    rng = np.random.default_rng(seed)
+    Kb = Nb - Mb
+    h = np.full((Mb, Nb), -1, dtype=np.int64)
+    h[:, Kb:] = _parity_part(Mb, Nb, 1, 0)
+    for i in range(Mb):
+        parity = int((h[i, Kb:] >= 0).sum())
+        want = (full_row_degree if i == 0 else other_degree) - parity
+        cols = rng.choice(Kb, size=min(Kb, max(0, want)), replace=False)
+        h[i, cols] = rng.integers(0, Z, len(cols))
+    return h.astype(np.int16)

@@ -74,6 +74,16 @@ def test_validation_errors_without_gpu():
     assert rc == P.LDPC_ERANGE
     rc, _ = _call_decode(np.zeros((2, 4), np.int16), 300)    # Z beyond the kernel limit
     assert rc == P.LDPC_ERANGE
+    # the limits themselves are accepted (F = 0: validation only), one beyond is not
+    assert _call_decode(np.zeros((2, 4), np.int16), 256, F=0)[0] == P.LDPC_OK
+    assert _call_decode(np.zeros((2, 4), np.int16), 257, F=0)[0] == P.LDPC_ERANGE
+    assert _call_decode(synth.limit_code(16, 32, 8, 18, 6, 1), 8, F=0)[0] == P.LDPC_OK
+    assert _call_decode(np.zeros((17, 40), np.int16)[:, :32], 8, F=0)[0] == P.LDPC_ERANGE   # 17 block rows
+    assert _call_decode(synth.limit_code(6, 32, 8, 26, 6, 1), 8, F=0)[0] == P.LDPC_OK
+    deg27 = synth.limit_code(5, 32, 8, 26, 6, 1)
+    deg27[0, :] = 0                                          # a block row of check degree 32
+    rc, msg = _call_decode(deg27, 8, F=0)
+    assert rc == P.LDPC_ERANGE and "more than 26" in msg
 
 
 def test_null_device_pointers_rejected():

@@ -302,3 +302,46 @@ def test_batch_mixed_families(with_heavy):
                 s = slice(off[f], off[f] + Ns[c])
                 assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], \
                     (path, codes[c][0], f)
+
+
+def test_batch_at_size_limits():
+    # codes at the kernels' limits (Z = 256, 32 block columns; 16 block rows,
+    # or a block row of check degree 26) beside a small code in one code set
+    codes = [("16 rows", 256, synth.limit_code(16, 32, 256, 18, 6, 86)),
+             ("degree 26", 256, synth.limit_code(6, 32, 256, 26, 6, 76)),
+             ("wifi 1/2", 27, synth.wifi_code("1/2", 27))]
+    cs = P.Codeset([(h, Z) for _, Z, h in codes])
+    F = 30
+    rng = np.random.default_rng(12)
+    cid = rng.integers(0, len(codes), F).astype(np.int32)
+    Ns = np.array([h.shape[1] * Z for _, Z, h in codes])
+    off = np.zeros(F, np.int64)
+    off[1:] = np.cumsum(Ns[cid])[:-1]
+    llr = np.zeros(int(Ns[cid].sum()), np.float32)
+    per = {}
+    for c in range(len(codes)):
+        idx = np.flatnonzero(cid == c)
+        _, Z, h = codes[c]
+        _, _, l = oracle.llr_frames(h, Z, len(idx), 3.0, 95 + c)
+        for k, f in enumerate(idx):
+            llr[off[f]:off[f] + Ns[c]] = l[k]
+        per[c] = (idx, l)
+    d = lambda x: torch.from_numpy(x).to(DEV)
+    for path in ("f32", "i8"):
+        if path == "f32":
+            bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=6, alpha=0.75, early_term=True)
+        else:
+            bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(oracle.quantize_i8(llr)), max_iter=6, offset=1,
+                                                 early_term=True)
+        torch.cuda.synchronize()
+        bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+        for c, (idx, l) in per.items():
+            _, Z, h = codes[c]
+            if path == "f32":
+                wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+            else:
+                wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=6, offset=1, early_term=True)
+            for k, f in enumerate(idx):
+                s = slice(off[f], off[f] + Ns[c])
+                assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], \
+                    (path, codes[c][0], f)

@@ -289,3 +289,20 @@ def test_int8_column_weight_boundary(Mb, heavy):
         _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=12, offset=1, early_term=True))
     finally:
         P.ldpc_cache_clear()
+
+
+@pytest.mark.parametrize("Mb,deg0", [(16, 18), (6, 26)])
+def test_decoders_at_size_limits(Mb, deg0):
+    # 32 block columns and Z = 256 (N = 8192, one frame per workgroup), with
+    # 16 block rows or a block row of the maximum check degree 26; 5 frames
+    Z = 256
+    h = synth.limit_code(Mb, 32, Z, deg0, 6, 70 + Mb)
+    _, _, llr = oracle.llr_frames(h, Z, 5, 2.0 if Mb == 16 else 4.0, 80 + Mb)
+    q = oracle.quantize_i8(llr)
+    for et in (True, False):
+        got = P.ldpc_decode_f32(h, Z, _gpu(llr), max_iter=6, alpha=0.75, early_term=et)
+        torch.cuda.synchronize()
+        _assert_f32_parity(got, oracle.decode_f32(h, Z, llr, max_iter=6, alpha=0.75, early_term=et))
+        got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=6, offset=1, early_term=et)
+        torch.cuda.synchronize()
+        _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=6, offset=1, early_term=et))

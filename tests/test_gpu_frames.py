@@ -63,3 +63,16 @@ def test_quantizer_bit_exact():
     x[40:44] = [1e30, -1e30, -0.0, 0.0]
     got = P.ldpc_quantize_i8(torch.from_numpy(x).to(DEV), 4.0).cpu().numpy()
     assert np.array_equal(got, oracle.quantize_i8(x, 4.0))
+
+
+@pytest.mark.parametrize("Mb,deg0", [(16, 18), (6, 26)])
+def test_encoder_at_size_limits(Mb, deg0):
+    # 32 block columns, Z = 256 (N = 8192); 16 block rows, or a block row of
+    # the maximum check degree 26
+    Z = 256
+    h = synth.limit_code(Mb, 32, Z, deg0, 6, 70 + Mb)
+    assert (h[0] >= 0).sum() == deg0
+    K = (32 - Mb) * Z
+    info = synth.info_bits(3, K, 71)
+    got = P.ldpc_encode(h, Z, torch.from_numpy(info).to(DEV)).cpu().numpy()
+    assert np.array_equal(got, oracle.encode(h, Z, info))
