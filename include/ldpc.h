@@ -250,6 +250,16 @@ int ldpc_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *it
                      int64_t N, int64_t K, int64_t *counters, void *stream);
 
 /*
+ * Measurement utility (no counterpart in the paper): LDS read bandwidth.
+ * Launches `blocks` workgroups of 256 threads; each thread reads
+ * rounds * 8 16-byte words from a 64 KB LDS buffer and writes a checksum to
+ * out[block * 256 + thread] (device f32 [blocks * 256]). Bytes read =
+ * blocks * 256 * rounds * 128; time the call on `stream` with events.
+ * LDPC_EINVAL unless 1 <= blocks, rounds <= 2^20.
+ */
+int ldpc_lds_probe(int blocks, int rounds, float *out, void *stream);
+
+/*
  * Fallback: the frames whose ok flag is 0 after a decode are decoded again
  * from their channel LLRs with fresh state by plain min-sum (FP32 weight
  * alpha; int8 offset or wq/16 as for ldpc_decode_i8) with early termination

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
     "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
-    "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset",
+    "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset", "ldpc_lds_probe",
     "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16",
     "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_decode_f32_packed", "ldpc_decode_i8_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
     "EXPORTS",
@@ -39,6 +39,7 @@ EXPORTS = {
     "ldpc_random_bits": ([_u64, _i64, _i64, _p, _p], _i32),
     "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p, _p, _p], _i32),
     "ldpc_frame_stats": ([_p, _p, _p, _p, _i64, _i64, _i64, _p, _p], _i32),
+    "ldpc_lds_probe": ([_i32, _i32, _p, _p], _i32),
     "ldpc_fallback_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_fallback_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
@@ -420,6 +421,16 @@ def ldpc_frame_stats(bits, info, iters=None, ok=None, counters=None, stream=None
                                   _opt(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)), F, N, K,
                                   _dev(counters, torch.int64, "counters", (4,)), _stream(stream)), "ldpc_frame_stats")
     return counters
+
+
+def ldpc_lds_probe(blocks, rounds, out=None, stream=None):
+    """LDS read bandwidth probe (blocks * 256 * rounds * 128 bytes read);
+    returns the checksum buffer f32 [blocks * 256]."""
+    torch = _torch()
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda") if out is None else out
+    _check(lib().ldpc_lds_probe(int(blocks), int(rounds), _dev(out, torch.float32, "out", (blocks * 256,)),
+                                _stream(stream)), "ldpc_lds_probe")
+    return out
 
 
 def _work(F, device):

@@ -284,6 +284,38 @@ int launch_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *
     return check_launch(__func__);
 }
 
+// LDS read bandwidth probe: each thread of a 256-thread workgroup reads
+// 16-byte words of a 64 KB LDS buffer, 8 per round at fixed offsets from a
+// base that moves every round (so the loads cannot be hoisted), and folds
+// them into a checksum with three-input bit operations (two per read, so
+// the ALU stays below the LDS rate). Indices stay below 3840 of 4096.
+__global__ __launch_bounds__(256) void k_lds_probe(float *out, int rounds)
+{
+    __shared__ uint4 buf[4096];
+    const int t = threadIdx.x;
+    for (int k = t; k < 4096; k += 256)
+        buf[k] = make_uint4(k, k * 3u, k * 5u, k * 7u);
+    __syncthreads();
+    uint32_t a0 = 0, a1 = 0;
+    int base = t;
+    for (int k = 0; k < rounds; ++k) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint4 v = buf[base + u * 256];
+            a0 = __builtin_amdgcn_bitop3_b32(a0, v.x, v.y, 0x96);
+            a1 = __builtin_amdgcn_bitop3_b32(a1, v.z, v.w, 0x96);
+        }
+        base = (base + 64) & 2047;
+    }
+    out[blockIdx.x * 256 + t] = (float)(a0 ^ a1);
+}
+
+int launch_lds_probe(int blocks, int rounds, float *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_lds_probe, dim3((unsigned)blocks), dim3(256), 0, stream, out, rounds);
+    return check_launch(__func__);
+}
+
 int launch_compact_failed(const uint8_t *ok, int64_t F, int64_t *out, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_compact_failed, dim3(1), dim3(1024), 0, stream, ok, F, out);

@@ -562,6 +562,16 @@ int ldpc_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *it
                          "ldpc_frame_stats");
 }
 
+int ldpc_lds_probe(int blocks, int rounds, float *out, void *stream)
+{
+    clear_error();
+    if (blocks < 1 || rounds < 1 || blocks > (1 << 20) || rounds > (1 << 20))
+        return fail(LDPC_EINVAL, "blocks and rounds must be in [1, 2^20]");
+    if (bad_ptrs({out}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_lds_probe(blocks, rounds, out, (hipStream_t)stream), "ldpc_lds_probe");
+}
+
 namespace {
 
 // Re-decodes, from their channel LLRs and with fresh state, the frames whose

@@ -90,6 +90,7 @@ int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, floa
 int launch_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
                        int64_t N, int64_t K, int64_t *counters, hipStream_t stream);
 int launch_compact_failed(const uint8_t *ok, int64_t F, int64_t *out, hipStream_t stream);
+int launch_lds_probe(int blocks, int rounds, float *out, hipStream_t stream);
 
 // Run-time specialised decode kernels (jit.cpp). path: 0 FP32, 1 int8;
 // mode as in jit_decode.hip. LDPC_JIT=0 in the environment disables them.

@@ -84,6 +84,9 @@ def test_validation_errors_without_gpu():
     deg27[0, :] = 0                                          # a block row of check degree 32
     rc, msg = _call_decode(deg27, 8, F=0)
     assert rc == P.LDPC_ERANGE and "more than 26" in msg
+    L = P.lib()
+    assert L.ldpc_lds_probe(0, 1, None, None) == P.LDPC_EINVAL    # the LDS probe validates on the host too
+    assert L.ldpc_lds_probe(1, 1, None, None) == P.LDPC_EINVAL
 
 
 def test_null_device_pointers_rejected():

@@ -76,3 +76,25 @@ def test_encoder_at_size_limits(Mb, deg0):
     info = synth.info_bits(3, K, 71)
     got = P.ldpc_encode(h, Z, torch.from_numpy(info).to(DEV)).cpu().numpy()
     assert np.array_equal(got, oracle.encode(h, Z, info))
+
+
+def test_lds_probe_reads_what_it_claims():
+    # the bandwidth probe's checksum for a small launch, recomputed: thread t
+    # folds words base + u*256 (u < 8) of buf[k] = (k, 3k, 5k, 7k), base
+    # starting at t and advancing by 64 modulo 2048 each round
+    blocks, rounds = 2, 5
+    got = P.ldpc_lds_probe(blocks, rounds).cpu().numpy()
+    k = np.arange(4096, dtype=np.uint64)
+    buf = np.stack([k, 3 * k, 5 * k, 7 * k], axis=1).astype(np.uint32)
+    want = np.zeros(blocks * 256, np.float32)
+    for t in range(256):
+        a0 = a1 = np.uint32(0)
+        base = t
+        for _ in range(rounds):
+            for u in range(8):
+                v = buf[base + u * 256]
+                a0 ^= v[0] ^ v[1]
+                a1 ^= v[2] ^ v[3]
+            base = (base + 64) & 2047
+        want[t] = want[256 + t] = np.float32(a0 ^ a1)
+    assert np.array_equal(got, want)
