@@ -39,7 +39,6 @@ ALG_OPS_PER_EDGE_ITER = 10
 # Non-packed 32-bit VALU issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-# LDS: 256 CUs x 128 B/clk x 2.4 GHz.
 # LDS read peak: 256 CUs x 256 B/clk x 2.4 GHz. gfx950 reads twice CDNA3's
 # 128 B/clk per CU: the LDS probe (ldpc_lds_probe) measures 144 TB/s, 92%
 # of this figure and above the 128 B/clk one.
