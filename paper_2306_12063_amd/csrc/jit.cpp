@@ -427,15 +427,19 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
 DecodeLaunch plan_nms(const Sched &sc)
 {
     // one frame per thread group; the adjoint keeps L and gL (FP32) for the
-    // workgroup's frames in LDS, frame-minor with an odd row stride
+    // workgroup's frames in LDS, frame-minor with an odd row stride, and one
+    // slot of weight-gradient sums per wave
     DecodeLaunch best{};
     double best_util = -1.0;
     for (int G = 1; G * sc.Z <= kMaxThreads && G <= 64; ++G) {
         const int FWp = G | 1;
-        const size_t lds = 2 * (size_t)sc.N * FWp * sizeof(float);
-        if (lds > (size_t)kLdsBudget)
+        const size_t frames_lds = 2 * (size_t)sc.N * FWp * sizeof(float);
+        if (frames_lds > (size_t)kLdsBudget)
             break;
         const int threads = ((G * sc.Z + 63) / 64) * 64;
+        const size_t lds = frames_lds + (size_t)(threads / 64) * sc.Mb * sc.Nb * sizeof(float);
+        if (lds > 64 * 1024)
+            break;
         const double util = (double)(G * sc.Z) / threads;
         if (util > best_util + 1e-9) {
             best_util = util;
@@ -499,7 +503,7 @@ int launch_nms_bwd(const Sched &sc, const uint8_t *cw, int64_t F, int T, const f
     if ((rc = launch(bwd, (unsigned)nwg, lc.threads, stream, a, "nms adjoint")))
         return rc;
     void *ar[] = {(void *)&partial, (void *)&nwg, (void *)&nw, (void *)&grad_w};
-    return launch(red, (unsigned)((nw + 255) / 256), 256, stream, ar, "nms gradient sum");
+    return launch(red, (unsigned)((nw + 63) / 64), 1024, stream, ar, "nms gradient sum");
 }
 
 }  // namespace ldpc

@@ -13,14 +13,18 @@
 // after every iteration. Early termination is off.
 //
 // Weight gradients: each lane holds one term per weight and iteration; the
-// terms are summed across the wave (DPP), then per workgroup in LDS; each
-// workgroup stores its sums and a reduction kernel adds them up.
+// terms are summed across the wave (DPP), each wave stores its sums in its
+// own LDS slot, the workgroup adds its waves' sums in wave order and stores
+// them, and a reduction kernel adds the workgroups' sums in a fixed order:
+// the gradient is the same on every run.
 //
 // Checkpoint of iteration t (taken when it starts), per frame: L (N FP32)
 // and the compressed row state (raw minima m1, m2 and sign/argmin word,
-// one triple per check row). The adjoint restores it, recomputes the
-// iteration keeping each row's Q values in registers, then runs the layers
-// in reverse:
+// one triple per check row). The adjoint restores it and recomputes the
+// iteration; each row's state after its update, plus the index of the
+// second smallest |Q| and the parity of the Q signs, is all the backward
+// needs of Q (|Q| enters only through the two minima, Q's sign is the
+// message's sign times the parity). Then it runs the layers in reverse:
 //   G_e = gL[n_e] + gR_e                      (R_e feeds L and the next Q)
 //   gw[t][i][col_e] += G_e * sgn_e * m_e
 //   gm_e = G_e * sgn_e * w[t][i][col_e]
@@ -98,15 +102,27 @@ __device__ __forceinline__ float sigmoid(float z)
 //   sg     at ((t*F + f) * CK) + N + 2M    M words
 constexpr int CK = N + 3 * M;
 
+// The backward keeps, per check row, the index a2 of the second smallest |Q|
+// and the parity of Q's signs. With at most 21 edges per row they fit in the
+// unused bits 21..26 of the sign/argmin word (a2 at 21, parity at 26), else in
+// a word of their own.
+constexpr bool PACK = MAXD <= 21;
+constexpr int NWAVE = (LDPC_THREADS + 63) / 64;
+
 // One layer of the forward for the thread's check row. Writes new L values
-// to LDS and the new compressed state; if QS is given, stores the row's Q
-// values there (backward recompute).
+// to LDS and the new compressed state; with KEEP (backward recompute) also
+// a2, the index of the second smallest |Q| (lowest index first among equal
+// values, as for the smallest), and the parity of Q's signs: packed into sgs
+// (PACK) or as aux = a2 | parity << 5.
+template <bool KEEP>
 __device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls, const float *__restrict__ w,
-                                          float &m1s, float &m2s, u32 &sgs, float *QS)
+                                          float &m1s, float &m2s, u32 &sgs, u32 &aux)
 {
     const int d = kDeg[i];
     int ix[MAXD];
     float Q[MAXD];
+    if (KEEP)
+        asm volatile("" : "+v"(r), "+v"(rb));   // opaque: recompute the addresses, do not keep them all live
 #pragma unroll
     for (int e = 0; e < MAXD; ++e)
         if (e < d)
@@ -122,13 +138,15 @@ __device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls
         const u32 ro = __float_as_uint(mag) | ((sgs << (32 - d + e)) & 0x80000000u);
         Q[e] = Ls[ix[e]] - __uint_as_float(ro);
     }
-    u32 idx = 0, neg = 0;
+    u32 idx = 0, idx2 = 0, neg = 0;
     float m1 = __builtin_inff(), m2 = __builtin_inff();
 #pragma unroll
     for (int e = 0; e < MAXD; ++e) {
         if (e >= d)
             continue;
         const float a = __builtin_fabsf(Q[e]);
+        if (KEEP)
+            idx2 = (a < m1) ? idx : ((a < m2) ? (u32)e : idx2);
         idx = (a < m1) ? (u32)e : idx;
         m2 = __builtin_amdgcn_fmed3f(a, m1, m2);
         m1 = __builtin_fminf(m1, a);
@@ -143,12 +161,14 @@ __device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls
         const float mag = w[(t * MB + i) * NB + kCol[i][e]] * ((idx == (u32)e) ? m2 : m1);
         const u32 rn = __float_as_uint(mag) | ((__float_as_uint(Q[e]) ^ parbit) & 0x80000000u);
         Ls[ix[e]] = Q[e] + __uint_as_float(rn);
-        if (QS)
-            QS[e] = Q[e];
     }
     m1s = m1;
     m2s = m2;
     sgs = (neg ^ ((0u - par) & ((1u << d) - 1u))) | (idx << 27);
+    if (KEEP && PACK)
+        sgs |= (idx2 << 21) | (par << 26);
+    if (KEEP && !PACK)
+        aux = idx2 | (par << 5);
 }
 
 extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
@@ -192,10 +212,13 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
                 ck[N + 2 * M + i * Z + r] = __uint_as_float(ssg[i]);
             }
         }
+        // layer 0 rewrites L values other threads are copying out above
+        __syncthreads();
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
+            u32 unused;
             if (on)
-                fwd_layer(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], nullptr);
+                fwd_layer<false>(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], unused);
             __syncthreads();
         }
         // per-frame loss of this iteration: thread r sums variables j*Z + r
@@ -247,34 +270,38 @@ extern "C" __global__ __launch_bounds__(256) void ldpc_nms_loss_reduce(const flo
         loss[t] = (float)(red[0] / ((double)T * (double)F * (double)N));
 }
 
-extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
+// Two waves per SIMD: the per-edge message gradients and the row state of
+// one iteration exceed 256 registers by a few dozen for the larger codes;
+// spilling those costs less than running one wave per SIMD.
+extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void ldpc_nms_bwd(
     const u8 *__restrict__ cw, const i64 F, const int T, const float *__restrict__ w,
     const float *__restrict__ ckpt, const float *__restrict__ dloss, float *__restrict__ partial)
 {
     __shared__ float Ls[N * FWP];
     __shared__ float gL[N * FWP];
-    __shared__ float gw[MB * NB];
+    __shared__ float gw[NWAVE][MB * NB];   // per wave: its sums of the iteration's weight terms
     const int tid = threadIdx.x;
+    const int wave = tid >> 6;
     const int g = tid / Z;
     const int r = tid - g * Z;
     const i64 f = (i64)blockIdx.x * G + g;
     const bool on = g < G && f < F;
     const int rb = r * FWP + g;
     const double inv = 1.0 / ((double)T * (double)F * (double)N);
-    float gR[ED];
-    float QS[ED];
+    float gR[ED];   // d loss / d R_e of the iteration being reversed
 #pragma unroll
     for (int k = 0; k < ED; ++k)
         gR[k] = 0.0f;
     for (int n = tid; n < N * FWP; n += LDPC_THREADS)
         gL[n] = 0.0f;
-    for (int k = tid; k < MB * NB; k += LDPC_THREADS)
-        gw[k] = 0.0f;
+    for (int k = tid; k < NWAVE * MB * NB; k += LDPC_THREADS)
+        gw[k / (MB * NB)][k % (MB * NB)] = 0.0f;   // weights without an edge stay 0
     __syncthreads();
     for (int t = T - 1; t >= 0; --t) {
-        // restore the start of iteration t and recompute it, keeping Q
+        // restore the start of iteration t and recompute it; afterwards the
+        // row state is iteration t's own
         float sm1[MB], sm2[MB];
-        u32 ssg[MB];
+        u32 ssg[MB], aux[PACK ? 1 : MB];
         if (on) {
             const float *ck = ckpt + ((i64)t * F + f) * CK;
 #pragma unroll
@@ -291,7 +318,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             if (on)
-                fwd_layer(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], QS + edge_off(i));
+                fwd_layer<true>(i, t, r, rb, Ls, w, sm1[i], sm2[i], ssg[i], aux[PACK ? 0 : i]);
             __syncthreads();
         }
         // the loss reads L after iteration t directly
@@ -314,54 +341,32 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
             for (int e = 0; e < MAXD; ++e)
                 gwc[e] = 0.0f;
             if (on) {
-                const float *Q = QS + edge_off(i);
                 float *gr = gR + edge_off(i);
-                int ix[MAXD];
+                int ix[MAXD], rr = r, rbb = rb;
+                asm volatile("" : "+v"(rr), "+v"(rbb));
 #pragma unroll
                 for (int e = 0; e < MAXD; ++e)
                     if (e < d)
-                        ix[e] = gather(i, e, r, rb);
-                // first and second smallest |Q| (values v1, v2 at a1, a2),
-                // lowest index first
-                int a1 = 0, a2 = 1;
-                float v1 = __builtin_fabsf(Q[0]), v2 = __builtin_fabsf(Q[1]);
-                if (v2 < v1) {
-                    a1 = 1;
-                    a2 = 0;
-                    const float tmp = v1;
-                    v1 = v2;
-                    v2 = tmp;
-                }
-                u32 neg = (__float_as_uint(Q[0]) >> 31) ^ (__float_as_uint(Q[1]) >> 31);
-#pragma unroll
-                for (int e = 2; e < MAXD; ++e) {
-                    if (e >= d)
-                        continue;
-                    const float a = __builtin_fabsf(Q[e]);
-                    if (a < v1) {
-                        a2 = a1;
-                        v2 = v1;
-                        a1 = e;
-                        v1 = a;
-                    } else if (a < v2) {
-                        a2 = e;
-                        v2 = a;
-                    }
-                    neg ^= __float_as_uint(Q[e]) >> 31;
-                }
+                        ix[e] = gather(i, e, rr, rbb);
+                // smallest and second smallest |Q| (v1 at a1, v2 at a2), the
+                // message signs (bit d-1-e of sw) and the parity of Q's signs
+                const float v1 = sm1[i], v2 = sm2[i];
+                const u32 sw = ssg[i];
+                const u32 ax = PACK ? sw >> 21 : aux[PACK ? 0 : i];
+                const u32 a1 = sw >> 27, a2 = ax & 31u, par = (ax >> 5) & 1u;
                 float gQ1 = 0.0f, gQ2 = 0.0f, gl[MAXD];
 #pragma unroll
                 for (int e = 0; e < MAXD; ++e) {
                     if (e >= d)
                         continue;
                     gl[e] = gL[ix[e]];
-                    const float sg = ((neg ^ (__float_as_uint(Q[e]) >> 31)) & 1u) ? -1.0f : 1.0f;
-                    const float m = (e == a1) ? v2 : v1;
+                    const float sg = ((sw >> (d - 1 - e)) & 1u) ? -1.0f : 1.0f;
+                    const float m = ((u32)e == a1) ? v2 : v1;
                     const float Ge = gl[e] + gr[e];
                     const float wv = w[(t * MB + i) * NB + kCol[i][e]];
                     gwc[e] = Ge * sg * m;
                     const float gm = Ge * sg * wv;
-                    if (e == a1)
+                    if ((u32)e == a1)
                         gQ2 += gm;
                     else
                         gQ1 += gm;
@@ -370,47 +375,72 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_bwd(
                 for (int e = 0; e < MAXD; ++e) {
                     if (e >= d)
                         continue;
-                    const float ga = (e == a1) ? gQ1 : ((e == a2) ? gQ2 : 0.0f);
-                    const float sq = Q[e] < 0.0f ? -1.0f : 1.0f;
+                    const float ga = ((u32)e == a1) ? gQ1 : (((u32)e == a2) ? gQ2 : 0.0f);
+                    const float sq = (((sw >> (d - 1 - e)) ^ par) & 1u) ? -1.0f : 1.0f;
                     const float gq = gl[e] + ga * sq;
                     gL[ix[e]] = gq;
                     gr[e] = -gq;
                 }
             }
-            // one LDS atomic per wave and weight: every lane of the workgroup
-            // adds to the same weights, so summing across the wave first
-            // avoids 64-way serialised atomics on one address
+            // every lane of the workgroup has a term for the same weights:
+            // the wave sums them (DPP) and stores the sum in its own slot,
+            // which no other wave writes (no atomics, a fixed order)
 #pragma unroll
             for (int e = 0; e < MAXD; ++e) {
                 if (e >= d)
                     continue;
                 const float s = wave_sum(gwc[e]);
                 if ((tid & 63) == 0)
-                    atomicAdd(&gw[i * NB + kCol[i][e]], s);
+                    gw[wave][i * NB + kCol[i][e]] = s;
             }
             __syncthreads();
         }
-        // this iteration's weight gradient of the workgroup's frames, summed
-        // over workgroups by ldpc_nms_grad_reduce (global atomics from every
-        // workgroup on the same few thousand weights would serialise)
+        // this iteration's weight gradient of the workgroup's frames (its
+        // waves' sums in wave order), summed over workgroups by
+        // ldpc_nms_grad_reduce
         for (int k = tid; k < MB * NB; k += LDPC_THREADS) {
-            partial[((i64)blockIdx.x * T + t) * (MB * NB) + k] = gw[k];
-            gw[k] = 0.0f;
+            float s = gw[0][k];
+#pragma unroll
+            for (int v = 1; v < NWAVE; ++v)
+                s += gw[v][k];
+            partial[((i64)blockIdx.x * T + t) * (MB * NB) + k] = s;
         }
         __syncthreads();
     }
 }
 
 // grad_w[k] = sum over the adjoint's workgroups b of partial[b][k], k over
-// the T*MB*NB weights, in workgroup order (the same sum on every run).
-extern "C" __global__ void ldpc_nms_grad_reduce(const float *__restrict__ partial, const i64 nwg, const int nw,
-                                                float *__restrict__ grad_w)
+// the T*MB*NB weights. A workgroup of 1024 threads takes 64 consecutive
+// weights (one per lane, coalesced); wave v adds the workgroups b = v,
+// v + 16, ... in order, then the 16 wave sums are added in wave order: the
+// same sum on every run.
+extern "C" __global__ __launch_bounds__(1024) void ldpc_nms_grad_reduce(const float *__restrict__ partial,
+                                                                       const i64 nwg, const int nw,
+                                                                       float *__restrict__ grad_w)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nw)
-        return;
+    __shared__ double red[16][64];
+    const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (i64 b = 0; b < nwg; ++b)
-        s += (double)partial[b * nw + k];
-    grad_w[k] = (float)s;
+    if (k < nw) {
+        i64 b = v;
+        for (; b + 48 < nwg; b += 64) {   // four loads in flight
+            const float x0 = partial[b * nw + k], x1 = partial[(b + 16) * nw + k];
+            const float x2 = partial[(b + 32) * nw + k], x3 = partial[(b + 48) * nw + k];
+            s += (double)x0;
+            s += (double)x1;
+            s += (double)x2;
+            s += (double)x3;
+        }
+        for (; b < nwg; b += 16)
+            s += (double)partial[b * nw + k];
+    }
+    red[v][lane] = s;
+    __syncthreads();
+    if (v == 0 && k < nw) {
+        double t = red[0][lane];
+        for (int u = 1; u < 16; ++u)
+            t += red[u][lane];
+        grad_w[k] = (float)t;
+    }
 }

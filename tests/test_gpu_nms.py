@@ -49,6 +49,21 @@ def test_constant_weights_equal_plain_decoder():
     assert torch.equal(post, p2)
 
 
+def test_checkpoint_holds_posteriors_of_each_iteration():
+    # the checkpoint of iteration t keeps L as it was before the iteration:
+    # with every weight 0.75 that is the plain decoder's posterior after t
+    # iterations (the channel LLRs for t = 0)
+    h, cw, llr, w = _case("1/2", 81, 600, 6, 1.5, 17)
+    Z, (F, N), T = 81, llr.shape, 6
+    _, ckpt, _ = P.ldpc_nms_fwd(h, Z, _gpu(llr), _gpu(cw), _gpu(w))
+    ck = ckpt.view(torch.float32)[: T * F * (N + 3 * h.shape[0] * Z)].view(T, F, -1)[:, :, :N]
+    assert torch.equal(ck[0], _gpu(llr))
+    for t in range(1, T):
+        _, post, _, _ = P.ldpc_decode_f32(h, Z, _gpu(llr), max_iter=t, alpha=0.75, early_term=False)
+        torch.cuda.synchronize()
+        assert torch.equal(ck[t], post), t
+
+
 def _grad_close(g, ref):
     floor = 1e-6 * np.abs(ref).max()
     bad = np.abs(g - ref) > 1e-3 * np.abs(ref) + floor
@@ -67,6 +82,36 @@ def test_adjoint_matches_oracle_gradient(rate, Z, F, T):
     g = g.cpu().numpy().astype(np.float64)
     assert (g[np.broadcast_to(h < 0, g.shape)] == 0).all()
     _grad_close(g, ref)
+
+
+def test_adjoint_row_degree_above_21():
+    # rows of more than 21 edges keep the second-minimum index and the sign
+    # parity beside the row's sign word instead of inside it
+    h = synth.limit_code(4, 30, 12, 26, 8, 41)
+    Z, F, T = 12, 40, 4
+    _, cw, llr = oracle.llr_frames(h, Z, F, 3.0, 43)
+    w = (0.75 + 0.15 * np.random.default_rng(44).uniform(-1, 1, (T,) + h.shape)).astype(np.float32)
+    loss, ckpt, post = P.ldpc_nms_fwd(h, Z, _gpu(llr), _gpu(cw), _gpu(w), want_post=True)
+    g = P.ldpc_nms_bwd(h, Z, _gpu(cw), _gpu(w), ckpt, torch.ones(T, dtype=torch.float32, device=DEV))
+    torch.cuda.synchronize()
+    _, ref, want_post = oracle.nms_train(h, Z, llr.astype(np.float64), cw, w.astype(np.float64), fwd_f32=True,
+                                         grad=True, post=True)
+    assert int((h >= 0).sum(axis=1).max()) == 26
+    assert np.array_equal(post.cpu().numpy(), want_post.astype(np.float32))
+    _grad_close(g.cpu().numpy().astype(np.float64), ref)
+
+
+def test_adjoint_is_deterministic():
+    # several waves per workgroup and many workgroups: the same gradient bits
+    # on every run
+    h, cw, llr, w = _case("1/2", 81, 300, 6, 1.5, 13, jitter=0.15)
+    loss, ckpt, _ = P.ldpc_nms_fwd(h, 81, _gpu(llr), _gpu(cw), _gpu(w))
+    dloss = torch.ones(6, dtype=torch.float32, device=DEV)
+    g1 = P.ldpc_nms_bwd(h, 81, _gpu(cw), _gpu(w), ckpt, dloss).clone()
+    for _ in range(3):
+        g2 = P.ldpc_nms_bwd(h, 81, _gpu(cw), _gpu(w), ckpt, dloss)
+        torch.cuda.synchronize()
+        assert torch.equal(g1, g2)
 
 
 def test_adjoint_weights_per_iteration_loss():
