@@ -352,11 +352,16 @@ DecodeLaunch make_h2_launch(const Sched &sc, int G, int max_threads)
     return lc;
 }
 
+static DecodeLaunch weighted_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode);
+
 DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
 {
+    DecodeLaunch out = lc;
     if (lc.h2 && (path != 1 || mode == 2 || !h2_eligible(sc)))
-        return single_frame_launch(sc);
-    return lc;
+        out = single_frame_launch(sc);
+    if ((path == 0 && mode == 1) || (path == 1 && mode == 2))
+        out = weighted_layout(sc, out, path, mode);
+    return out;
 }
 
 DecodeLaunch jit_default_launch(const Sched &sc, int path)
@@ -400,6 +405,51 @@ int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mo
         *vgprs = v;
     }
     return LDPC_OK;
+}
+
+// A weight table costs registers (the row's weights, read from LDS next to
+// the messages): a layout chosen or tuned for the plain kernel can need more
+// than 168 VGPRs in the weighted one and so lose a wave per SIMD, which this
+// latency-bound loop pays for (measured: 20.8 against 33.0 Gbit/s for the
+// WiMAX-shaped rate-1/2 code at Z=96). Above 168 the layout keeps its frames
+// and takes the deepest address hoist of Mb/2, Mb/4 and 0 whose weighted
+// kernel, compiled for three waves per SIMD, does not spill; none at all
+// hoisted is the last resort. Chosen once per code, layout and mode.
+static DecodeLaunch weighted_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
+{
+    static std::mutex mu;
+    static std::unordered_map<std::string, DecodeLaunch> memo;
+    const std::string key = prelude(sc, lc, path, mode);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = memo.find(key);
+        if (it != memo.end())
+            return it->second;
+    }
+    DecodeLaunch best = lc;
+    size_t bytes = 0;
+    int vgprs = 0;
+    if (lc.waves == 0 && jit_decode_scratch(sc, lc, path, mode, &bytes, &vgprs) == LDPC_OK && vgprs > 168) {
+        const int cands[3] = {sc.Mb / 2, sc.Mb / 4, 0};
+        for (int k = 0; k < 3; ++k) {
+            if (cands[k] >= lc.hoist || (k > 0 && cands[k] == cands[k - 1]))
+                continue;
+            DecodeLaunch c = lc;
+            c.hoist = cands[k];
+            c.waves = 3;
+            if (jit_decode_scratch(sc, c, path, mode, &bytes, &vgprs) != LDPC_OK)
+                break;
+            if (bytes == 0 || cands[k] == 0) {
+                if (bytes != 0)
+                    c.waves = 0;   // unhinted: no spill, fewer waves
+                best = c;
+                break;
+            }
+        }
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    memo[key] = best;
+    return best;
 }
 
 int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mode, const void *llr,
