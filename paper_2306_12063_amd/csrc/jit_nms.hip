@@ -121,8 +121,9 @@ __device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls
     const int d = kDeg[i];
     int ix[MAXD];
     float Q[MAXD];
-    if (KEEP)
-        asm volatile("" : "+v"(r), "+v"(rb));   // opaque: recompute the addresses, do not keep them all live
+    // opaque: the addresses are recomputed per layer instead of all being
+    // kept live across iterations (that would cost a register per edge)
+    asm volatile("" : "+v"(r), "+v"(rb));
 #pragma unroll
     for (int e = 0; e < MAXD; ++e)
         if (e < d)

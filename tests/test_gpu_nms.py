@@ -114,6 +114,38 @@ def test_adjoint_is_deterministic():
         assert torch.equal(g1, g2)
 
 
+def test_training_batch_size():
+    # the training configuration (WiMAX-shaped rate 1/2, Z = 96, batch 4096,
+    # T = 10): the forward's posteriors equal the weight-table decoder's bit
+    # for bit; the gradient, a mean over frames, equals the mean of the
+    # gradients of four 1024-frame quarters (a property at any size), and a
+    # 64-frame batch matches the oracle
+    h = synth.wimax_code("1/2", 96)
+    Z, F, T = 96, 4096, 10
+    _, cw, llr = oracle.llr_frames(h, Z, F, 2.0, 23)
+    w = (0.75 + 0.1 * np.random.default_rng(24).uniform(-1, 1, (T,) + h.shape)).astype(np.float32)
+    dloss = torch.ones(T, dtype=torch.float32, device=DEV)
+    cwg, llrg, wg = _gpu(cw), _gpu(llr), _gpu(w)
+    _, ckpt, post = P.ldpc_nms_fwd(h, Z, llrg, cwg, wg, want_post=True)
+    g = P.ldpc_nms_bwd(h, Z, cwg, wg, ckpt, dloss).cpu().numpy().astype(np.float64)
+    _, p2, _, _ = P.ldpc_decode_f32(h, Z, llrg, max_iter=T, early_term=False, w=wg)
+    torch.cuda.synchronize()
+    assert torch.equal(post, p2)
+    parts = []
+    for q in range(4):
+        sl = slice(q * 1024, (q + 1) * 1024)
+        _, ck, _ = P.ldpc_nms_fwd(h, Z, llrg[sl], cwg[sl], wg)
+        parts.append(P.ldpc_nms_bwd(h, Z, cwg[sl], wg, ck, dloss).cpu().numpy().astype(np.float64))
+    mean = sum(parts) / 4
+    floor = 1e-6 * np.abs(mean).max()
+    assert (np.abs(g - mean) <= 1e-4 * np.abs(mean) + floor).all()
+    _, ck, _ = P.ldpc_nms_fwd(h, Z, llrg[:64], cwg[:64], wg)
+    g64 = P.ldpc_nms_bwd(h, Z, cwg[:64], wg, ck, dloss).cpu().numpy().astype(np.float64)
+    _, ref, _ = oracle.nms_train(h, Z, llr[:64].astype(np.float64), cw[:64], w.astype(np.float64), fwd_f32=True,
+                                 grad=True)
+    _grad_close(g64, ref)
+
+
 def test_adjoint_weights_per_iteration_loss():
     # d/dw of sum_t a_t loss[t] with arbitrary a_t: linear in a
     h, cw, llr, w = _case("1/2", 27, 20, 4, 1.0, 2, jitter=0.1)
