@@ -179,12 +179,13 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
  * timed compiled for one more wave per SIMD (waves = 3 above 168 VGPRs,
  * else 4); such a variant may spill at most 32 bytes of registers per lane
  * (scratch memory, extra HBM traffic) and is kept only if it is at least 5%
- * faster than the fastest layout that does not spill. Decoders given a
- * weight table (w, wq_table) keep the layout's frames but, where the
- * weighted kernel needs more than 168 VGPRs, hoist fewer block rows' gather
- * addresses (Mb/2, Mb/4 or 0: the deepest that fits three waves per SIMD
- * without spilling); the first such call on a code compiles up to four
- * kernel variants to find it.
+ * faster than the fastest layout that does not spill. Layouts the tuner
+ * has not timed for the kernel at hand -- the default layout of an untuned
+ * code, and any layout used with a weight table (w, wq_table) -- keep their
+ * frames but, where the kernel needs more than 168 VGPRs, hoist fewer block
+ * rows' gather addresses (Mb/2, Mb/4 or 0: the deepest that fits three
+ * waves per SIMD without spilling); the first such call on a code compiles
+ * up to four kernel variants to find it.
  * Synchronises `stream`; allocates and frees temporary device buffers.
  * LDPC_ERANGE if run-time specialisation is disabled (LDPC_JIT=0).
  */

@@ -352,15 +352,18 @@ DecodeLaunch make_h2_launch(const Sched &sc, int G, int max_threads)
     return lc;
 }
 
-static DecodeLaunch weighted_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode);
+static DecodeLaunch three_wave_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode);
 
 DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
 {
     DecodeLaunch out = lc;
     if (lc.h2 && (path != 1 || mode == 2 || !h2_eligible(sc)))
         out = single_frame_launch(sc);
-    if ((path == 0 && mode == 1) || (path == 1 && mode == 2))
-        out = weighted_layout(sc, out, path, mode);
+    // a layout the tuner did not time for this kernel: the default layout,
+    // or a weighted mode (its kernel needs more registers than the plain one)
+    const bool weighted = (path == 0 && mode == 1) || (path == 1 && mode == 2);
+    if (weighted || !out.tuned)
+        out = three_wave_layout(sc, out, path, mode);
     return out;
 }
 
@@ -407,15 +410,16 @@ int jit_decode_scratch(const Sched &sc, const DecodeLaunch &lc, int path, int mo
     return LDPC_OK;
 }
 
-// A weight table costs registers (the row's weights, read from LDS next to
-// the messages): a layout chosen or tuned for the plain kernel can need more
-// than 168 VGPRs in the weighted one and so lose a wave per SIMD, which this
-// latency-bound loop pays for (measured: 20.8 against 33.0 Gbit/s for the
-// WiMAX-shaped rate-1/2 code at Z=96). Above 168 the layout keeps its frames
-// and takes the deepest address hoist of Mb/2, Mb/4 and 0 whose weighted
-// kernel, compiled for three waves per SIMD, does not spill; none at all
-// hoisted is the last resort. Chosen once per code, layout and mode.
-static DecodeLaunch weighted_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
+// Layouts the tuner has not timed for the kernel at hand -- the default
+// layout, and any layout in a weighted mode, where the row's weights (read
+// from LDS next to the messages) cost registers -- can need more than 168
+// VGPRs and so lose a wave per SIMD, which this latency-bound loop pays for
+// (measured: FP32 weight table of the WiMAX-shaped rate-1/2 code at Z=96,
+// 20.8 against 33.0 Gbit/s). Above 168 the layout keeps its frames and
+// takes the deepest address hoist of Mb/2, Mb/4 and 0 whose kernel, compiled
+// for three waves per SIMD, does not spill; none at all hoisted is the last
+// resort. Chosen once per code, layout and mode.
+static DecodeLaunch three_wave_layout(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
 {
     static std::mutex mu;
     static std::unordered_map<std::string, DecodeLaunch> memo;

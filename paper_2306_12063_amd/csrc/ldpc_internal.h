@@ -58,6 +58,7 @@ struct DecodeLaunch {
     int hoist = 0;  // specialised kernels: block rows whose gather addresses stay in registers
     int h2 = 0;     // fixed point with two frames per lane in packed FP16 (G = frame pairs, FW = 2G)
     int waves = 0;  // specialised kernels: occupancy target in waves per SIMD (0: the compiler's choice)
+    int tuned = 0;  // chosen by the autotuner for this code's plain kernel
 };
 
 // Largest column weight (block rows with an edge in a block column).

@@ -197,6 +197,7 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         rc = fail(LDPC_ERANGE, "autotune: no decode layout fits this code");
         goto done;
     }
+    best_lc.tuned = 1;
     set_tuned_launch(sc, path, best_lc);
     *best = best_lc;
     *best_ms = best_t;
