@@ -86,14 +86,24 @@ __device__ __forceinline__ float wave_sum(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
-__device__ __forceinline__ float softplus(float z) { return __builtin_fmaxf(z, 0.0f) + log1pf(expf(-__builtin_fabsf(z))); }
-
+// Softplus and sigmoid on the transcendental unit: v_exp_f32 and v_log_f32
+// (base 2) and v_rcp_f32 are accurate to about one ulp, and the loss and its
+// gradient are means over every bit of every frame, where these errors stay
+// orders of magnitude below the loss and gradient tolerances. (The library
+// expf and log1pf cost several times the decoder's own arithmetic per bit.)
+__device__ __forceinline__ float exp_neg_abs(float z)   // e^-|z| in (0, 1]
+{
+    return __builtin_amdgcn_exp2f(-__builtin_fabsf(z) * 1.44269504088896341f);
+}
+__device__ __forceinline__ float softplus(float z)
+{
+    return __builtin_fmaxf(z, 0.0f) + __builtin_amdgcn_logf(1.0f + exp_neg_abs(z)) * 0.693147180559945309f;
+}
 __device__ __forceinline__ float sigmoid(float z)
 {
-    if (z >= 0.0f)
-        return 1.0f / (1.0f + expf(-z));
-    const float e = expf(z);
-    return e / (1.0f + e);
+    const float e = exp_neg_abs(z);
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    return z >= 0.0f ? r : e * r;
 }
 
 // Checkpoint layout for iteration t and frame f (all FP32 words):
