@@ -154,6 +154,30 @@ def _assert_exact(got, want):
         assert np.array_equal(g, w), f"{name} differs"
 
 
+def test_register_fitted_layouts():
+    # the WiMAX-shaped rate-1/2 code at Z = 96 is where untuned and weighted
+    # layouts are re-derived from the kernels' registers (FP32 weight table:
+    # 6 block rows hoisted at three waves; int8 table and the packed int8
+    # default: 3): bit-exact, with early termination on and off
+    h = synth.wimax_code("1/2", 96)
+    Z, T = 96, 10
+    _, _, llr = oracle.llr_frames(h, Z, 40, 1.8, 91)
+    q = oracle.quantize_i8(llr)
+    rng = np.random.default_rng(92)
+    w = (0.75 + 0.1 * rng.uniform(-1, 1, (T,) + h.shape)).astype(np.float32)
+    wt = rng.integers(8, 17, (T,) + h.shape).astype(np.uint8)
+    for et in (True, False):
+        got = P.ldpc_decode_f32(h, Z, _gpu(llr), max_iter=T, early_term=et, w=_gpu(w))
+        torch.cuda.synchronize()
+        _assert_f32_parity(got, oracle.decode_f32(h, Z, llr, max_iter=T, early_term=et, w=w))
+        got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=T, wq_table=_gpu(wt), early_term=et)
+        torch.cuda.synchronize()
+        _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=T, wq_table=wt, early_term=et))
+        got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=T, offset=1, early_term=et)
+        torch.cuda.synchronize()
+        _assert_exact(got, oracle.decode_i8(h, Z, q, max_iter=T, offset=1, early_term=et))
+
+
 @pytest.mark.parametrize("rate", list(synth.WIFI_RATES))
 @pytest.mark.parametrize("mode", [dict(offset=1, wq=0), dict(offset=0, wq=12), dict(offset=2, wq=0)])
 def test_int8_bit_exact(rate, mode):
