@@ -482,7 +482,8 @@ DecodeLaunch plan_nms(const Sched &sc)
 {
     // one frame per thread group; the adjoint keeps L and gL (FP32) for the
     // workgroup's frames in LDS, frame-minor with an odd row stride, and one
-    // slot of weight-gradient sums per wave
+    // slot of weight-gradient sums per 16-lane row (gfx950 gives a workgroup
+    // up to 160 KiB of LDS; 96 KiB keeps two adjoint workgroups per CU)
     DecodeLaunch best{};
     double best_util = -1.0;
     for (int G = 1; G * sc.Z <= kMaxThreads && G <= 64; ++G) {
@@ -491,8 +492,8 @@ DecodeLaunch plan_nms(const Sched &sc)
         if (frames_lds > (size_t)kLdsBudget)
             break;
         const int threads = ((G * sc.Z + 63) / 64) * 64;
-        const size_t lds = frames_lds + (size_t)(threads / 64) * sc.Mb * sc.Nb * sizeof(float);
-        if (lds > 64 * 1024)
+        const size_t lds = frames_lds + (size_t)(threads / 16) * sc.Mb * sc.Nb * sizeof(float);
+        if (lds > 96 * 1024)
             break;
         const double util = (double)(G * sc.Z) / threads;
         if (util > best_util + 1e-9) {

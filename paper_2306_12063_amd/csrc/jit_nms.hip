@@ -13,10 +13,10 @@
 // after every iteration. Early termination is off.
 //
 // Weight gradients: each lane holds one term per weight and iteration; the
-// terms are summed across the wave (DPP), each wave stores its sums in its
-// own LDS slot, the workgroup adds its waves' sums in wave order and stores
-// them, and a reduction kernel adds the workgroups' sums in a fixed order:
-// the gradient is the same on every run.
+// terms are summed within each 16-lane row of the wave (DPP row shifts),
+// each row stores its sum in its own LDS slot, the workgroup adds the slots
+// in a fixed order and stores the sums, and a reduction kernel adds the
+// workgroups' sums in a fixed order: the gradient is the same on every run.
 //
 // Checkpoint of iteration t (taken when it starts), per frame: L (N FP32)
 // and the compressed row state (raw minima m1, m2 and sign/argmin word,
@@ -65,25 +65,22 @@ __device__ __forceinline__ int gather(int i, int e, int r, int rb)
     return rb + base - ((r >= Z - kShift[i][e]) ? ZFW : 0);
 }
 
-// Sum of v over the 64 lanes of the wave (every lane active): inclusive sums
-// within rows of 16 lanes by DPP row shifts, then row_bcast:15 and
-// row_bcast:31 carry the row totals up, leaving the total in lane 63. Lanes
-// a DPP source does not cover (row edge, rows outside the row mask) add 0.
-template <int CTRL, int ROW_MASK>
+// Sum of v over each row of 16 lanes, in lane 15 of the row: inclusive sums
+// by DPP row shifts (lanes a shift does not reach add 0). Stopping at the
+// rows saves the cross-row broadcast steps, whose masked form costs three
+// instructions each: the rows' sums go to LDS instead.
+template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v)
 {
-    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
-                                                                     0xf, false));
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                                     false));
 }
-__device__ __forceinline__ float wave_sum(float v)
+__device__ __forceinline__ float row_sum(float v)
 {
-    v = dpp_add<0x111, 0xf>(v);   // row_shr:1
-    v = dpp_add<0x112, 0xf>(v);   // row_shr:2
-    v = dpp_add<0x114, 0xf>(v);   // row_shr:4
-    v = dpp_add<0x118, 0xf>(v);   // row_shr:8
-    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    v = dpp_add<0x111>(v);   // row_shr:1
+    v = dpp_add<0x112>(v);   // row_shr:2
+    v = dpp_add<0x114>(v);   // row_shr:4
+    return dpp_add<0x118>(v);   // row_shr:8
 }
 
 // Softplus and sigmoid on the transcendental unit: v_exp_f32 and v_log_f32
@@ -118,6 +115,7 @@ constexpr int CK = N + 3 * M;
 // a word of their own.
 constexpr bool PACK = MAXD <= 21;
 constexpr int NWAVE = (LDPC_THREADS + 63) / 64;
+constexpr int NSLOT = 4 * NWAVE;   // 16-lane rows of the workgroup
 
 // One layer of the forward for the thread's check row. Writes new L values
 // to LDS and the new compressed state; with KEEP (backward recompute) also
@@ -290,9 +288,9 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_wave
 {
     __shared__ float Ls[N * FWP];
     __shared__ float gL[N * FWP];
-    __shared__ float gw[NWAVE][MB * NB];   // per wave: its sums of the iteration's weight terms
+    __shared__ float gw[NSLOT][MB * NB];   // per 16-lane row: its sums of the iteration's weight terms
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int slot = tid >> 4;
     const int g = tid / Z;
     const int r = tid - g * Z;
     const i64 f = (i64)blockIdx.x * G + g;
@@ -305,7 +303,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_wave
         gR[k] = 0.0f;
     for (int n = tid; n < N * FWP; n += LDPC_THREADS)
         gL[n] = 0.0f;
-    for (int k = tid; k < NWAVE * MB * NB; k += LDPC_THREADS)
+    for (int k = tid; k < NSLOT * MB * NB; k += LDPC_THREADS)
         gw[k / (MB * NB)][k % (MB * NB)] = 0.0f;   // weights without an edge stay 0
     __syncthreads();
     for (int t = T - 1; t >= 0; --t) {
@@ -394,25 +392,25 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_wave
                 }
             }
             // every lane of the workgroup has a term for the same weights:
-            // the wave sums them (DPP) and stores the sum in its own slot,
-            // which no other wave writes (no atomics, a fixed order)
+            // each 16-lane row sums them (DPP) and stores the sum in its own
+            // slot, which nothing else writes (no atomics, a fixed order)
 #pragma unroll
             for (int e = 0; e < MAXD; ++e) {
                 if (e >= d)
                     continue;
-                const float s = wave_sum(gwc[e]);
-                if ((tid & 63) == 0)
-                    gw[wave][i * NB + kCol[i][e]] = s;
+                const float s = row_sum(gwc[e]);
+                if ((tid & 15) == 15)
+                    gw[slot][i * NB + kCol[i][e]] = s;
             }
             __syncthreads();
         }
         // this iteration's weight gradient of the workgroup's frames (its
-        // waves' sums in wave order), summed over workgroups by
+        // rows' sums in row order), summed over workgroups by
         // ldpc_nms_grad_reduce
         for (int k = tid; k < MB * NB; k += LDPC_THREADS) {
             float s = gw[0][k];
 #pragma unroll
-            for (int v = 1; v < NWAVE; ++v)
+            for (int v = 1; v < NSLOT; ++v)
                 s += gw[v][k];
             partial[((i64)blockIdx.x * T + t) * (MB * NB) + k] = s;
         }
