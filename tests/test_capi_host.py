@@ -113,3 +113,18 @@ def test_ebn0_at_fer_interpolation():
     assert ebn0_at_fer(pts) == pytest.approx(2.5)
     assert ebn0_at_fer(pts, target=1e-2) == pytest.approx(2.0)
     assert ebn0_at_fer(pts[:2]) is None
+
+
+@pytest.mark.parametrize("code,Z,G", [(("wimax", "1/2"), 96, 2), (("wifi", "5/6"), 81, 3), (("wifi", "1/2"), 27, 7)])
+def test_nms_checkpoint_size(code, Z, G):
+    # the training buffer: per iteration and frame L (N floats) and the raw
+    # row state (3 M), the per-frame loss terms (T F), and the adjoint's
+    # per-workgroup partial gradients (T Mb Nb per workgroup of G frames; G
+    # fills the most lanes of whole waves: 2 x 96 = 192, 3 x 81 = 243 of 256,
+    # 7 x 27 = 189 of 192)
+    h = synth.wimax_code(code[1], Z) if code[0] == "wimax" else synth.wifi_code(code[1], Z)
+    Mb, Nb = h.shape
+    N, M = Nb * Z, Mb * Z
+    for F, T in [(4096, 10), (37, 4), (1, 1)]:
+        want = 4 * (T * F * (N + 3 * M) + T * F + ((F + G - 1) // G) * T * Mb * Nb)
+        assert P.ldpc_nms_ckpt_bytes(h, Z, F, T) == want
