@@ -128,3 +128,19 @@ def test_nms_checkpoint_size(code, Z, G):
     for F, T in [(4096, 10), (37, 4), (1, 1)]:
         want = 4 * (T * F * (N + 3 * M) + T * F + ((F + G - 1) // G) * T * Mb * Nb)
         assert P.ldpc_nms_ckpt_bytes(h, Z, F, T) == want
+
+
+def test_no_cpu_fallback_for_host_tensors():
+    # every step runs in the library's kernels: host tensors are refused
+    # before any call, never decoded on the CPU
+    import torch
+    h = synth.wifi_code("1/2", 27)
+    calls = [lambda: P.ldpc_decode_f32(h, 27, torch.zeros((4, 648))),
+             lambda: P.ldpc_decode_i8(h, 27, torch.zeros((4, 648), dtype=torch.int8)),
+             lambda: P.ldpc_encode(h, 27, torch.zeros((4, 324), dtype=torch.uint8)),
+             lambda: P.ldpc_quantize_i8(torch.zeros(16)),
+             lambda: P.ldpc_nms_fwd(h, 27, torch.zeros((4, 648)), torch.zeros((4, 648), dtype=torch.uint8),
+                                    torch.full((3, 12, 24), 0.75))]
+    for call in calls:
+        with pytest.raises(TypeError, match="GPU tensor"):
+            call()
