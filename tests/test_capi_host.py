@@ -144,3 +144,22 @@ def test_no_cpu_fallback_for_host_tensors():
     for call in calls:
         with pytest.raises(TypeError, match="GPU tensor"):
             call()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # a copy of the binding without libldpc.so: the first library call raises
+    # (there is no fallback implementation to drop to)
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(os.path.dirname(HEADER), "..", "paper_2306_12063_amd")
+    dst = tmp_path / "paper_2306_12063_amd"
+    dst.mkdir()
+    for f in os.listdir(src):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(src, f), dst / f)
+    code = ("import paper_2306_12063_amd as P\n"
+            "try:\n    P.lib()\nexcept ImportError as e:\n    print('raised:', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120,
+                         env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert "raised:" in out.stdout and "not built" in out.stdout, out.stdout + out.stderr
