@@ -53,6 +53,7 @@ def lib():
                 "orc_decode_flood_f64": [p, i32, i32, i32, p, i64, i32, f64, i32, p, p, p, p],
                 "orc_decode_flood_i8": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
                 "orc_quantize_i8": [p, p, i64, f32],
+                "orc_quantize_weights": [p, p, i64],
                 "orc_decode_q16": [p, i32, i32, i32, p, i64, i32, i32, i32, i32, p, p, p, p],
                 "orc_quantize_q16": [p, p, i64, f32, i32],
                 "orc_shift_packed": [p, p, i64, i32, i32],
@@ -267,6 +268,15 @@ def encode_packed(hbm, Z, info_packed):
     cw = np.zeros((F, (Nb * Z + 7) // 8), np.uint8)
     _check(lib().orc_encode_packed(_ptr(h), Mb, Nb, Z, _ptr(info_packed), _ptr(cw), F), "encode_packed")
     return cw
+
+
+def quantize_weights(w):
+    """1/16-step weights of the fixed-point decoder: clamp(rint(16 w), 0, 31),
+    half to even; NaN -> 0 (oracle.c orc_quantize_weights)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    q = np.zeros(w.shape, np.uint8)
+    _check(lib().orc_quantize_weights(_ptr(w), _ptr(q), w.size), "quantize_weights")
+    return q
 
 
 def quantize_i8(llr, scale=4.0):

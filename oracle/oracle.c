@@ -706,6 +706,25 @@ int orc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale)
     return ORC_OK;
 }
 
+/* Learned weights in 1/16 steps for the fixed-point decoder (the int8
+ * decoder's normalisation wq/16, Sec. 5 fixed point): wq = clamp(rint(16 w),
+ * 0, 31), rint rounding half to even. 16 w is exact in float (a power-of-two
+ * scaling). A NaN weight maps to 0, +inf to 31 and -inf to 0. */
+int orc_quantize_weights(const float *w, uint8_t *wq, int64_t n)
+{
+    if (n < 0 || (n > 0 && (!w || !wq)))
+        return ORC_EINVAL;
+    for (int64_t k = 0; k < n; k++) {
+        float v = rintf(16.0f * w[k]);
+        if (!(v >= 0.0f))   /* negative or NaN */
+            v = 0.0f;
+        if (v > 31.0f)
+            v = 31.0f;
+        wq[k] = (uint8_t)v;
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Learned normalised min-sum: loss and its exact gradient                  */
 /* ------------------------------------------------------------------------ */

@@ -61,3 +61,42 @@ def test_quantizer_rounds_half_to_even_and_clips():
     qb = oracle.quantize_i8(big, 4.0)
     assert qb.min() == -127 and qb.max() == 127
     assert np.array_equal(oracle.quantize_i8(-big, 4.0), -qb)
+
+
+def test_weight_quantizer_half_to_even_and_clamps():
+    # wq = clamp(rint(16 w), 0, 31) (the fixed-point decoder's 1/16-step
+    # normalisation): each case written out by hand from that definition.
+    cases = [
+        (0.75, 12),              # alpha = 0.75 is exactly 12/16
+        (0.5 / 16, 0),           # 0.5 -> 0 (half to even)
+        (1.5 / 16, 2),           # 1.5 -> 2
+        (2.5 / 16, 2),           # 2.5 -> 2
+        (3.5 / 16, 4),           # 3.5 -> 4
+        (12.5 / 16, 12),         # 12.5 -> 12
+        (13.5 / 16, 14),         # 13.5 -> 14
+        (30.5 / 16, 30),         # 30.5 -> 30
+        (31.5 / 16, 31),         # 31.5 -> 32, clamped to 31
+        (1.9375, 31),            # 31 exactly
+        (2.0, 31),               # 32 -> 31
+        (1e30, 31),
+        (float("inf"), 31),
+        (-0.01, 0),              # -0.16 -> -0 -> 0
+        (-0.5, 0),               # -8 -> 0
+        (-0.0, 0),
+        (float("-inf"), 0),
+        (float("nan"), 0),
+        (0.78, 12),              # 12.48 -> 12
+        (0.79, 13),              # 12.64 -> 13
+    ]
+    w = np.array([c[0] for c in cases], np.float32)
+    assert oracle.quantize_weights(w).tolist() == [c[1] for c in cases]
+
+
+def test_weight_quantizer_matches_numpy_rint():
+    # numpy's rint rounds half to even as well: the finite range agrees with
+    # np.clip(np.rint(16 w), 0, 31) element by element
+    w = np.linspace(-1.0, 3.0, 64000).astype(np.float32)
+    want = np.clip(np.rint(np.float32(16.0) * w), 0, 31).astype(np.uint8)
+    got = oracle.quantize_weights(w.reshape(16, -1)).ravel()
+    assert np.array_equal(got, want)
+    assert oracle.quantize_weights(w.reshape(16, -1)).shape == (16, 4000)
