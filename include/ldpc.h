@@ -357,6 +357,15 @@ int ldpc_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int 
  */
 int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *stream);
 
+/*
+ * Learned weights in 1/16 steps for the fixed-point decoder (the wq_table of
+ * ldpc_decode_i8, Sec. 5 fixed point with a learned normalisation):
+ * wq = clamp(rint(16 w), 0, 31), rounding half to even; a NaN weight gives 0.
+ * w: device f32 [n], wq: device u8 [n]. Returns LDPC_EINVAL for n < 0 or a
+ * null pointer with n > 0.
+ */
+int ldpc_quantize_weights(const float *w, uint8_t *wq, int64_t n, void *stream);
+
 /* Message for the last failing call on this host thread ("" if none). */
 const char *ldpc_last_error(void);
 

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
-    "ldpc_quantize_i8", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
+    "ldpc_quantize_i8", "ldpc_quantize_weights", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
     "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset", "ldpc_lds_probe",
     "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16",
     "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_decode_f32_packed", "ldpc_decode_i8_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
@@ -43,6 +43,7 @@ EXPORTS = {
     "ldpc_fallback_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_fallback_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_quantize_i8": ([_p, _p, _i64, _f32, _p], _i32),
+    "ldpc_quantize_weights": ([_p, _p, _i64, _p], _i32),
     "ldpc_autotune_decode": ([_p, _i32, _i32, _i32, _i32, _i32, _i64, _p, _p, _p], _i32),
     "ldpc_nms_ckpt_bytes": ([_p, _i32, _i32, _i32, _i64, _i32], C.c_size_t),
     "ldpc_nms_fwd": ([_p, _i32, _i32, _i32, _p, _p, _i64, _i32, _p, _p, C.c_size_t, _p, _p, _p], _i32),
@@ -383,6 +384,15 @@ def ldpc_quantize_i8(llr, scale=4.0, out=None, stream=None):
     out = torch.empty(llr.shape, dtype=torch.int8, device=llr.device) if out is None else out
     _check(lib().ldpc_quantize_i8(_dev(llr, torch.float32, "llr"), _dev(out, torch.int8, "q", llr.shape),
                                   llr.numel(), float(scale), _stream(stream)), "ldpc_quantize_i8")
+    return out
+
+
+def ldpc_quantize_weights(w, out=None, stream=None):
+    """1/16-step weights of the fixed-point decoder: u8 clamp(rint(16 w), 0, 31)."""
+    torch = _torch()
+    out = torch.empty(w.shape, dtype=torch.uint8, device=w.device) if out is None else out
+    _check(lib().ldpc_quantize_weights(_dev(w, torch.float32, "w"), _dev(out, torch.uint8, "wq", w.shape), w.numel(),
+                                       _stream(stream)), "ldpc_quantize_weights")
     return out
 
 

@@ -90,6 +90,19 @@ __global__ void k_quantize_i8(const float *__restrict__ in, int8_t *__restrict__
     out[i] = (int8_t)v;
 }
 
+// Learned weights in 1/16 steps for the fixed-point decoder:
+// wq = clamp(rint(16 w), 0, 31), half to even (16 w is exact). v_max_f32
+// returns the other operand for a NaN, so a NaN weight becomes 0.
+__global__ void k_quantize_weights(const float *__restrict__ in, uint8_t *__restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float v = rintf(16.0f * in[i]);
+    v = fminf(fmaxf(v, 0.0f), 31.0f);
+    out[i] = (uint8_t)v;
+}
+
 // Q_B-bit quantiser of the paper's fixed point: clamp(rint(scale x), +-qmax).
 __global__ void k_quantize_q16(const float *__restrict__ in, int16_t *__restrict__ out, int64_t n, float scale,
                                float qmax)
@@ -251,6 +264,12 @@ inline int grid_for(int64_t work, int threads) { return (int)((work + threads - 
 int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_quantize_i8, dim3(grid_for(n, 256)), dim3(256), 0, stream, llr, q, n, scale);
+    return check_launch(__func__);
+}
+
+int launch_quantize_weights(const float *w, uint8_t *wq, int64_t n, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_quantize_weights, dim3(grid_for(n, 256)), dim3(256), 0, stream, w, wq, n);
     return check_launch(__func__);
 }
 

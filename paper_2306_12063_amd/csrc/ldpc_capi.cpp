@@ -674,4 +674,16 @@ int ldpc_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, void *
     return device_status(launch_quantize_i8(llr, q, n, scale, (hipStream_t)stream), "ldpc_quantize_i8");
 }
 
+int ldpc_quantize_weights(const float *w, uint8_t *wq, int64_t n, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return fail(LDPC_EINVAL, "negative size");
+    if (n == 0)
+        return LDPC_OK;
+    if (bad_ptrs({w, wq}))
+        return fail(LDPC_EINVAL, "null device pointer");
+    return device_status(launch_quantize_weights(w, wq, n, (hipStream_t)stream), "ldpc_quantize_weights");
+}
+
 }  // extern "C"

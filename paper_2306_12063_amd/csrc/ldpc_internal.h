@@ -82,6 +82,7 @@ int launch_decode_i8(const Sched &sc, const DecodeLaunch &lc, const int8_t *llr,
                      int16_t *post, int32_t *iters, uint8_t *ok, hipStream_t stream);
 int launch_quantize_i8(const float *llr, int8_t *q, int64_t n, float scale, hipStream_t stream);
 int launch_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, int qmax, hipStream_t stream);
+int launch_quantize_weights(const float *w, uint8_t *wq, int64_t n, hipStream_t stream);
 int launch_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, hipStream_t stream);
 int launch_encode_packed(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
 int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);

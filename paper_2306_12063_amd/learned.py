@@ -25,8 +25,7 @@ from .nms import nms_loss, quantize_weights
 
 def awgn_params(ebn0_db, rate):
     """Per-frame noise deviation and LLR scale (FP32) for Eb/N0 values in dB."""
-    e = np.asarray(ebn0_db, dtype=np.float64)
-    s2 = 1.0 / (2.0 * rate * np.power(10.0, e / 10.0))
+    s2 = synth.sigma2_from_ebn0(np.asarray(ebn0_db, dtype=np.float64), rate)
     return np.sqrt(s2).astype(np.float32), (2.0 / s2).astype(np.float32)
 
 

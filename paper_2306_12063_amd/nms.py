@@ -9,7 +9,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import ldpc_nms_bwd, ldpc_nms_fwd
+from . import ldpc_nms_bwd, ldpc_nms_fwd, ldpc_quantize_weights
 
 
 class NMSLoss(torch.autograd.Function):
@@ -38,5 +38,6 @@ def nms_loss(w, llr, cw, hbm, Z):
 
 
 def quantize_weights(w):
-    """1/16-step weights for the int8 decoder: wq = clamp(rint(16 w), 0, 31)."""
-    return torch.clamp(torch.round(w * 16.0), 0, 31).to(torch.uint8)
+    """1/16-step weights for the int8 decoder, wq = clamp(rint(16 w), 0, 31),
+    computed by the library (ldpc_quantize_weights)."""
+    return ldpc_quantize_weights(w.detach().float().contiguous())

@@ -193,10 +193,14 @@ def std_normal(F: int, N: int, seed: int, dtype=np.float32) -> np.ndarray:
     return g.standard_normal(size=(F, N)).astype(dtype)
 
 
-def sigma2_from_ebn0(ebn0_db: float, rate: float) -> float:
+def sigma2_from_ebn0(ebn0_db, rate: float):
     """Noise variance for BPSK at Eb/N0 (dB) and code rate R:
-    sigma^2 = 1 / (2 R 10^(Eb/N0 / 10))."""
-    return 1.0 / (2.0 * rate * math.pow(10.0, ebn0_db / 10.0))
+    sigma^2 = 1 / (2 R 10^(Eb/N0 / 10)). A number gives a float, an array of
+    Eb/N0 values (one per frame) an array of the same shape (float64)."""
+    if np.ndim(ebn0_db) == 0:
+        return 1.0 / (2.0 * rate * math.pow(10.0, float(ebn0_db) / 10.0))
+    e = np.asarray(ebn0_db, dtype=np.float64)
+    return 1.0 / (2.0 * rate * np.power(10.0, e / 10.0))
 
 
 def heavy_column_code(Mb: int, heavy: int, Z: int, seed: int) -> np.ndarray:

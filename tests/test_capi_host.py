@@ -163,3 +163,11 @@ def test_missing_library_fails_loudly(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True, text=True, timeout=120,
                          env=dict(os.environ, PYTHONPATH=str(tmp_path)))
     assert "raised:" in out.stdout and "not built" in out.stdout, out.stdout + out.stderr
+
+
+def test_weight_quantizer_validation_without_gpu():
+    L = P.lib()
+    assert L.ldpc_quantize_weights(None, None, 0, None) == P.LDPC_OK    # empty: no-op
+    assert L.ldpc_quantize_weights(None, None, -1, None) == P.LDPC_EINVAL
+    assert L.ldpc_quantize_weights(None, None, 4, None) == P.LDPC_EINVAL
+    assert "null" in P.ldpc_last_error()

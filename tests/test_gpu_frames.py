@@ -98,3 +98,15 @@ def test_lds_probe_reads_what_it_claims():
             base = (base + 64) & 2047
         want[t] = want[256 + t] = np.float32(a0 ^ a1)
     assert np.array_equal(got, want)
+
+
+def test_weight_quantizer_bit_exact():
+    # the learned-weight quantiser (1/16 steps, half to even, clamp to
+    # [0, 31], NaN -> 0) against the oracle on ties, clamps, specials and a
+    # dense sweep, including a ragged tail of a 256-thread block
+    special = np.array([0.75, 0.5 / 16, 1.5 / 16, 2.5 / 16, 31.5 / 16, 2.0, 1e30, np.inf, -np.inf, np.nan, -0.0,
+                        -0.01, 0.78, 0.79], np.float32)
+    sweep = np.linspace(-1.0, 3.0, 100003).astype(np.float32)
+    for w in (special, sweep, sweep[:1], np.zeros(0, np.float32)):
+        got = P.ldpc_quantize_weights(torch.from_numpy(w).to(DEV)).cpu().numpy()
+        assert np.array_equal(got, oracle.quantize_weights(w))
