@@ -193,6 +193,28 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
                          int32_t out[7], float *ms, void *stream);
 
 /*
+ * Decode layouts, for reproducible runs and for checking every layout the
+ * autotuner may choose (the layouts change the launch shape and register
+ * use, never the arithmetic of Sec. 4).
+ * ldpc_decode_layouts: the layouts ldpc_autotune_decode times for this code
+ *   and path, in its order, each as the 7 integers of its out[7]; writes at
+ *   most `cap` rows to out (int32 [cap][7], host) and returns the total count
+ *   (>= 0) or a negative status. Compiles every candidate kernel (hipRTC) to
+ *   read its registers and spills; no device memory is touched.
+ * ldpc_set_decode_layout: makes `layout` (the 7 integers, as returned above
+ *   or by ldpc_autotune_decode) this process's layout for later
+ *   ldpc_decode_f32/_i8 calls on this code and path, as if the tuner had
+ *   chosen it; NULL restores the default layout. LDPC_EINVAL if FWp or
+ *   threads do not follow from G and KF, hoist is outside [0, Mb], waves is
+ *   not 0, 3 or 4, or packed FP16 is asked for on the FP32 path, with KF 2
+ *   or for a code of column weight above 15; LDPC_ERANGE if the layout does
+ *   not fit (threads, LDS).
+ * Both need run-time specialisation (LDPC_ERANGE if LDPC_JIT=0).
+ */
+int ldpc_decode_layouts(const int16_t *hbm, int Mb, int Nb, int Z, int path, int32_t *out, int cap);
+int ldpc_set_decode_layout(const int16_t *hbm, int Mb, int Nb, int Z, int path, const int32_t layout[7]);
+
+/*
  * Learned normalised min-sum (training). Weights w[T][Mb][Nb] (device f32)
  * replace the fixed normalisation: in iteration t (0-based) the message
  * leaving block column j of block row i is sgn * fl(w[t][i][j] * min), in the
@@ -295,13 +317,18 @@ int ldpc_fallback_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *ll
  * ldpc_batch_work_bytes: size of the device scratch buffer for F frames.
  * ldpc_decode_batch_f32 / _i8: decodes F frames; frame f belongs to code
  *   code_id[f] (device i32 [F]) and its N values start at element off[f]
- *   (device i64 [F]) of llr, and at the same offset in bits and post; iters
- *   and ok are [F]. Frames are grouped by code on the device and cut into work
- *   items that the workgroups of a persistent grid take from an atomic queue.
+ *   (device i64 [F]) of llr, and at the same offset in bits and post; llr,
+ *   bits and post (if given) hold n_llr elements each; iters and ok are [F].
+ *   Frames are grouped by code on the device and cut into work items that
+ *   the workgroups of a persistent grid take from an atomic queue.
  *   Arithmetic and arguments as ldpc_decode_f32 (alpha) / ldpc_decode_i8
- *   (offset, wq; no weight table). Frames whose code id is outside
- *   [0, ncodes) are not decoded. No host synchronisation: the call can be
- *   captured in a hipGraph. Calls that share a work buffer must not overlap.
+ *   (offset, wq; no weight table). A frame whose code id is outside
+ *   [0, ncodes), or whose values would not lie inside the n_llr elements
+ *   (off[f] < 0 or off[f] + N > n_llr; checked on the device), is not
+ *   decoded: its iters entry is set to -1 and its ok entry to 0, its bits and
+ *   posteriors are left as they are. No host synchronisation: the call can
+ *   be captured in a hipGraph. Calls that share a work buffer must not
+ *   overlap.
  */
 typedef struct ldpc_codeset ldpc_codeset;
 int ldpc_codeset_create(const int16_t *const *hbm, const int *Mb, const int *Nb, const int *Z, int ncodes,
@@ -310,28 +337,40 @@ void ldpc_codeset_destroy(ldpc_codeset *cs);
 int ldpc_codeset_info(const ldpc_codeset *cs, int code, int64_t out[8]);
 size_t ldpc_batch_work_bytes(const ldpc_codeset *cs, int64_t F);
 int ldpc_decode_batch_f32(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const float *llr,
-                          int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits, float *post,
-                          int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
+                          int64_t n_llr, int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits,
+                          float *post, int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
 int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const int8_t *llr,
-                         int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits, int16_t *post,
-                         int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
+                         int64_t n_llr, int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits,
+                         int16_t *post, int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
 
 /*
  * Batch layout autotuner (frames per work item and workgroup size of the
  * persistent kernel). Decodes the caller's batch -- same arguments as
  * ldpc_decode_batch_f32/_i8 for `path` 0/1 -- with alpha 0.75 (FP32) or
  * offset 1 (int8), early termination off, under each candidate layout:
- * workgroups of 192, 256, 384 or 512 threads, each code's work items
- * holding floor(threads / Z) frames (at most 64), and for 256 and 512
- * threads also half as many. Keeps the fastest
+ * workgroups of 192, 256, 384 or 512 threads (those at least as wide as
+ * the largest Z of the set), each code's work items holding
+ * floor(threads / Z) frames (at most 64), and for 256 and 512 threads also
+ * half as many. Keeps the fastest
  * for later batched decodes of `path` with this code set; out[2] receives
  * {threads, divisor} and *ms its time per decode. bits and iters receive the
  * last decode's results. Synchronises `stream`; the code set must not be in
  * use on another stream meanwhile (its tables are rebuilt).
  */
+/*
+ * ldpc_codeset_set_layout: makes one of the batch autotuner's layouts
+ * (threads in {192, 256, 384, 512} with divisor 1, or {256, 512} with
+ * divisor 2) the layout of later batched decodes of `path` with this code
+ * set, as if the tuner had chosen it (for reproducible runs, and to check
+ * every layout the tuner may choose). Rebuilds the path's device tables
+ * (allocates device memory); the code set must not be in use on another
+ * stream meanwhile. LDPC_EINVAL for another layout, LDPC_ERANGE if a code's
+ * Z exceeds the workgroup or its frames do not fit the LDS budget.
+ */
+int ldpc_codeset_set_layout(ldpc_codeset *cs, int path, int threads, int divisor);
 int ldpc_codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
-                          int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, size_t work_bytes,
-                          int32_t out[2], float *ms, void *stream);
+                          int64_t n_llr, int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work,
+                          size_t work_bytes, int32_t out[2], float *ms, void *stream);
 
 /*
  * The paper's own fixed point (Sec. 5): layered min-sum on int16 values,

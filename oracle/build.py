@@ -10,10 +10,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
 
+# -ffp-contract=off and -fno-fast-math: every product and sum rounded on its own
+FLAGS = ["-std=c99", "-O3", "-ffp-contract=off", "-fno-fast-math"]
+
+
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "oracle.c")
-    cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp", src, "-lm"]
+    cmd = (["gcc"] + FLAGS + ["-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp",
+                              src, "-lm"])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)

@@ -17,7 +17,8 @@ import numpy as np
 
 __all__ = [
     "LdpcError", "lib", "ldpc_code_info", "ldpc_encode", "ldpc_decode_f32", "ldpc_decode_i8",
-    "ldpc_quantize_i8", "ldpc_quantize_weights", "ldpc_autotune_decode", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
+    "ldpc_quantize_i8", "ldpc_quantize_weights", "ldpc_autotune_decode", "ldpc_decode_layouts",
+    "ldpc_set_decode_layout", "ldpc_nms_ckpt_bytes", "ldpc_nms_fwd", "ldpc_nms_bwd",
     "ldpc_random_bits", "ldpc_frame_stats", "ldpc_fallback_f32", "ldpc_fallback_i8", "Codeset", "ldpc_lds_probe",
     "ldpc_decode_flood_f32", "ldpc_decode_flood_i8", "ldpc_decode_q16", "ldpc_quantize_q16",
     "ldpc_encode_packed", "ldpc_shift_packed", "ldpc_decode_f32_packed", "ldpc_decode_i8_packed", "ldpc_awgn_llr", "ldpc_last_error", "ldpc_cache_clear",
@@ -52,10 +53,14 @@ EXPORTS = {
     "ldpc_codeset_destroy": ([_p], None),
     "ldpc_codeset_info": ([_p, _i32, _p], _i32),
     "ldpc_batch_work_bytes": ([_p, _i64], C.c_size_t),
-    "ldpc_decode_batch_f32": ([_p, _p, _p, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p], _i32),
-    "ldpc_decode_batch_i8": ([_p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p],
-                             _i32),
-    "ldpc_codeset_autotune": ([_p, _i32, _p, _p, _p, _i64, _i32, _p, _p, _p, C.c_size_t, _p, _p, _p], _i32),
+    "ldpc_decode_batch_f32": ([_p, _p, _p, _p, _i64, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, C.c_size_t, _p],
+                              _i32),
+    "ldpc_decode_batch_i8": ([_p, _p, _p, _p, _i64, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, C.c_size_t,
+                              _p], _i32),
+    "ldpc_codeset_set_layout": ([_p, _i32, _i32, _i32], _i32),
+    "ldpc_decode_layouts": ([_p, _i32, _i32, _i32, _i32, _p, _i32], _i32),
+    "ldpc_set_decode_layout": ([_p, _i32, _i32, _i32, _i32, _p], _i32),
+    "ldpc_codeset_autotune": ([_p, _i32, _p, _p, _p, _i64, _i64, _i32, _p, _p, _p, C.c_size_t, _p, _p, _p], _i32),
     "ldpc_decode_flood_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_flood_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_q16": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p], _i32),
@@ -379,6 +384,37 @@ def ldpc_autotune_decode(hbm, Z, path="f32", max_iter=10, F=16384, stream=None):
                 h2=int(out[5]), waves=int(out[6]), ms=float(ms[0]))
 
 
+_LAYOUT_KEYS = ("G", "KF", "FWp", "threads", "hoist", "h2", "waves")
+
+
+def ldpc_decode_layouts(hbm, Z, path="f32"):
+    """Every layout the decode autotuner times for this code and path, as
+    dicts with the keys of ldpc_autotune_decode (compiles each candidate)."""
+    h = _hbm(hbm)
+    p = {"f32": 0, "i8": 1}[path]
+    n = lib().ldpc_decode_layouts(_hptr(h), h.shape[0], h.shape[1], Z, p, None, 0)
+    if n < 0:
+        _check(n, "ldpc_decode_layouts")
+    out = np.zeros((max(n, 1), 7), np.int32)
+    m = lib().ldpc_decode_layouts(_hptr(h), h.shape[0], h.shape[1], Z, p, out.ctypes.data_as(C.c_void_p), n)
+    if m < 0:
+        _check(m, "ldpc_decode_layouts")
+    return [dict(zip(_LAYOUT_KEYS, (int(v) for v in row))) for row in out[:n]]
+
+
+def ldpc_set_decode_layout(hbm, Z, path, layout):
+    """Makes `layout` (a dict with the keys of ldpc_autotune_decode, or None
+    for the default) the decode layout of this code and path."""
+    h = _hbm(hbm)
+    p = {"f32": 0, "i8": 1}[path]
+    arr = None
+    if layout is not None:
+        arr = np.array([int(layout[k]) for k in _LAYOUT_KEYS], np.int32)
+    _check(lib().ldpc_set_decode_layout(_hptr(h), h.shape[0], h.shape[1], Z, p,
+                                        None if arr is None else arr.ctypes.data_as(C.c_void_p)),
+           "ldpc_set_decode_layout")
+
+
 def ldpc_quantize_i8(llr, scale=4.0, out=None, stream=None):
     torch = _torch()
     out = torch.empty(llr.shape, dtype=torch.int8, device=llr.device) if out is None else out
@@ -565,7 +601,7 @@ class Codeset:
         ok = torch.empty(F, dtype=torch.uint8, device=dev) if ok is None else ok
         fn = getattr(lib(), name)
         _check(fn(self._cs, _dev(code_id, torch.int32, "code_id", (F,)), _dev(off, torch.int64, "off", (F,)),
-                  _dev(llr, llr_dtype, "llr"), F, *args_mid, _dev(bits, torch.uint8, "bits", (total,)),
+                  _dev(llr, llr_dtype, "llr", (total,)), total, F, *args_mid, _dev(bits, torch.uint8, "bits", (total,)),
                   _opt(post, post_dtype, "post", (total,)), _dev(iters, torch.int32, "iters", (F,)),
                   _opt(ok, torch.uint8, "ok", (F,)), _dev(work, torch.uint8, "work"), work.numel(),
                   _stream(stream)), name)
@@ -593,12 +629,18 @@ class Codeset:
         ms = C.c_float()
         _check(lib().ldpc_codeset_autotune(self._cs, p, _dev(code_id, torch.int32, "code_id", (F,)),
                                            _dev(off, torch.int64, "off", (F,)),
-                                           _dev(llr, torch.float32 if p == 0 else torch.int8, "llr"), F,
-                                           int(max_iter), _dev(bits, torch.uint8, "bits"),
+                                           _dev(llr, torch.float32 if p == 0 else torch.int8, "llr"),
+                                           llr.numel(), F, int(max_iter), _dev(bits, torch.uint8, "bits"),
                                            _dev(iters, torch.int32, "iters"), _dev(work, torch.uint8, "work"),
                                            work.numel(), out.ctypes.data_as(C.c_void_p), C.byref(ms),
                                            _stream(stream)), "ldpc_codeset_autotune")
         return dict(threads=int(out[0]), divisor=int(out[1]), ms=float(ms.value))
+
+    def set_layout(self, path, threads, divisor=1):
+        """Makes one of the batch autotuner's layouts (threads, divisor) the
+        layout of later batched decodes of `path` (ldpc_codeset_set_layout)."""
+        p = {"f32": 0, "i8": 1}[path]
+        _check(lib().ldpc_codeset_set_layout(self._cs, p, int(threads), int(divisor)), "ldpc_codeset_set_layout")
 
     def decode_i8(self, code_id, off, llr, max_iter=10, offset=1, wq=0, early_term=True, bits=None, post=None,
                   iters=None, ok=None, work=None, want_post=True, stream=None):

@@ -38,6 +38,9 @@ struct ldpc_codeset {
 
 namespace ldpc {
 
+constexpr int kNumBatchLayouts = 6;
+extern const int kBatchLayouts[kNumBatchLayouts][2];
+
 namespace {
 
 struct CodeRec {
@@ -106,6 +109,10 @@ std::string batch_prelude(const ldpc_codeset &cs, int path, int mode)
 
 extern const char kJitBatchSource[];
 
+// Layouts of the persistent kernel the batch autotuner times: {workgroup
+// threads, divisor of the frames per work item}.
+const int kBatchLayouts[kNumBatchLayouts][2] = {{256, 1}, {192, 1}, {384, 1}, {512, 1}, {256, 2}, {512, 2}};
+
 // (Re)builds a path's device tables for a layout: workgroups of `threads`
 // threads, floor(threads / Z) / gdiv lane groups per work item (at most 64),
 // each holding one frame, or two on the packed-FP16 fixed-point path.
@@ -118,6 +125,9 @@ int build_tables(ldpc_codeset *cs, int path, int threads, int gdiv)
     size_t lds = 0;
     for (int c = 0; c < n; ++c) {
         const Sched &s = cs->sc[c];
+        // a frame's Z rows need Z threads of the workgroup
+        if (s.Z > threads)
+            return fail(LDPC_ERANGE, "code %d: Z=%d exceeds a %d-thread workgroup", c, s.Z, threads);
         int groups = std::max(1, std::min(64, threads / s.Z) / gdiv);
         // fewer groups per item where the posteriors (one column block of
         // padding included) would not fit the LDS budget
@@ -235,8 +245,9 @@ size_t batch_work_bytes(const ldpc_codeset *cs, int64_t F)
 }
 
 int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_t *code_id, const int64_t *off,
-                        const void *llr, int64_t F, int max_iter, float alpha, int offset, int wq, int et,
-                        uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, void *work, hipStream_t stream)
+                        const void *llr, int64_t n_llr, int64_t F, int max_iter, float alpha, int offset, int wq,
+                        int et, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, void *work,
+                        hipStream_t stream)
 {
     const std::string pre = batch_prelude(*cs, path, mode);
     hipFunction_t f_clear, f_hist, f_plan, f_items, f_scatter, f_dec;
@@ -257,12 +268,14 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
     int nwords = (int)hw;
     long long Fll = (long long)F;
     const void *codes = cs->d_codes[path], *etab = cs->d_etab[path];
+    long long nll = (long long)n_llr;
     void *a_clear[] = {(void *)&head, (void *)&nwords};
-    void *a_hist[] = {(void *)&code_id, (void *)&Fll, (void *)&nc, (void *)&head};
+    void *a_hist[] = {(void *)&code_id, (void *)&off, (void *)&codes, (void *)&nll, (void *)&Fll, (void *)&nc,
+                      (void *)&head};
     void *a_plan[] = {(void *)&codes, (void *)&nc, (void *)&head};
     void *a_items[] = {(void *)&codes, (void *)&nc, (void *)&head, (void *)&items};
-    void *a_scatter[] = {(void *)&code_id, (void *)&off,  (void *)&Fll,
-                         (void *)&nc,      (void *)&head, (void *)&perm, (void *)&offp};
+    void *a_scatter[] = {(void *)&code_id, (void *)&off,  (void *)&codes, (void *)&nll,   (void *)&Fll, (void *)&nc,
+                         (void *)&head,    (void *)&perm, (void *)&offp,  (void *)&iters, (void *)&ok};
     // frames per workgroup of the histogram and the scatter (FPB in jit_batch.hip)
     const unsigned fblocks = (unsigned)((F + 4095) / 4096);
     if ((rc = jit_launch(f_clear, (unsigned)((nwords + 255) / 256), 256, stream, a_clear, "batch clear")) ||
@@ -288,11 +301,14 @@ int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_
 // Times the batched decode of the caller's batch for each candidate layout
 // and keeps the fastest (tables rebuilt for it).
 int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
-                     int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, hipStream_t stream,
-                     int32_t out[2], float *best_ms)
+                     int64_t n_llr, int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work,
+                     hipStream_t stream, int32_t out[2], float *best_ms)
 {
-    static const int cand[][2] = {{256, 1}, {192, 1}, {384, 1}, {512, 1}, {256, 2}, {512, 2}};
-    constexpr int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    const int(*cand)[2] = kBatchLayouts;
+    constexpr int ncand = kNumBatchLayouts;
+    int maxz = 0;
+    for (int c = 0; c < cs->ncodes; ++c)
+        maxz = std::max(maxz, cs->sc[c].Z);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)
@@ -304,11 +320,13 @@ int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const i
     const char *lv = getenv("LDPC_TUNE_LOG");
     const bool log = lv && lv[0] == '1';
     for (int k = 0; k < ncand && rc == LDPC_OK; ++k) {
+        if (cand[k][0] < maxz)   // a frame's rows would not fit the workgroup
+            continue;
         if ((rc = build_tables(cs, path, cand[k][0], cand[k][1])))
             break;
         auto run = [&]() {
-            return launch_batch_decode(cs, path, 0, code_id, off, llr, F, max_iter, 0.75f, 1, 0, 0, bits, nullptr,
-                                       iters, nullptr, work, stream);
+            return launch_batch_decode(cs, path, 0, code_id, off, llr, n_llr, F, max_iter, 0.75f, 1, 0, 0, bits,
+                                       nullptr, iters, nullptr, work, stream);
         };
         if ((rc = run()))   // compiles the variant and warms the caches
             break;
@@ -399,13 +417,14 @@ size_t ldpc_batch_work_bytes(const ldpc_codeset *cs, int64_t F)
 }
 
 static int batch_common(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const void *llr,
-                        int64_t F, int max_iter, const void *bits, const int32_t *iters, void *work, size_t work_bytes)
+                        int64_t n_llr, int64_t F, int max_iter, const void *bits, const int32_t *iters, void *work,
+                        size_t work_bytes)
 {
     clear_error();
     if (!cs)
         return fail(LDPC_EINVAL, "null code set");
-    if (F < 0 || max_iter < 1)
-        return fail(LDPC_EINVAL, "F must be >= 0 and max_iter >= 1");
+    if (F < 0 || max_iter < 1 || n_llr < 0)
+        return fail(LDPC_EINVAL, "F and n_llr must be >= 0 and max_iter >= 1");
     if (F > ((int64_t)1 << 31) - 1)
         return fail(LDPC_ERANGE, "batch larger than 2^31 - 1 frames");
     if (F > 0 && (!code_id || !off || !llr || !bits || !iters || !work))
@@ -419,42 +438,62 @@ static int batch_common(const ldpc_codeset *cs, const int32_t *code_id, const in
 }
 
 int ldpc_decode_batch_f32(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const float *llr,
-                          int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits, float *post,
-                          int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
+                          int64_t n_llr, int64_t F, int max_iter, float alpha, int early_term, uint8_t *bits,
+                          float *post, int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
 {
-    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    int rc = batch_common(cs, code_id, off, llr, n_llr, F, max_iter, bits, iters, work, work_bytes);
     if (rc || F == 0)
         return rc;
-    return launch_batch_decode(cs, 0, 0, code_id, off, llr, F, max_iter, alpha, 0, 0, early_term, bits, post, iters,
-                               ok, work, (hipStream_t)stream);
+    return launch_batch_decode(cs, 0, 0, code_id, off, llr, n_llr, F, max_iter, alpha, 0, 0, early_term, bits, post,
+                               iters, ok, work, (hipStream_t)stream);
 }
 
 int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const int8_t *llr,
-                         int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits, int16_t *post,
-                         int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
+                         int64_t n_llr, int64_t F, int max_iter, int offset, int wq, int early_term, uint8_t *bits,
+                         int16_t *post, int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream)
 {
-    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    int rc = batch_common(cs, code_id, off, llr, n_llr, F, max_iter, bits, iters, work, work_bytes);
     if (rc || F == 0)
         return rc;
     if (offset < 0 || offset > 127 || wq < 0 || wq > 31)
         return fail(LDPC_EINVAL, "offset must be in [0, 127] and wq in [0, 31]");
-    return launch_batch_decode(cs, 1, wq > 0 ? 1 : 0, code_id, off, llr, F, max_iter, 0.0f, offset, wq, early_term,
-                               bits, post, iters, ok, work, (hipStream_t)stream);
+    return launch_batch_decode(cs, 1, wq > 0 ? 1 : 0, code_id, off, llr, n_llr, F, max_iter, 0.0f, offset, wq,
+                               early_term, bits, post, iters, ok, work, (hipStream_t)stream);
+}
+
+int ldpc_codeset_set_layout(ldpc_codeset *cs, int path, int threads, int divisor)
+{
+    clear_error();
+    if (!cs)
+        return fail(LDPC_EINVAL, "null code set");
+    if (path != 0 && path != 1)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    bool known = false;
+    for (int k = 0; k < kNumBatchLayouts; ++k)
+        known = known || (kBatchLayouts[k][0] == threads && kBatchLayouts[k][1] == divisor);
+    if (!known)
+        return fail(LDPC_EINVAL, "layout (%d threads, divisor %d) is not one of the batch autotuner's", threads,
+                    divisor);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != cs->device)
+        return fail(LDPC_EINVAL, "the code set belongs to device %d", cs->device);
+    return build_tables(cs, path, threads, divisor);
 }
 
 int ldpc_codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const int64_t *off, const void *llr,
-                          int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work, size_t work_bytes,
-                          int32_t out[2], float *ms, void *stream)
+                          int64_t n_llr, int64_t F, int max_iter, uint8_t *bits, int32_t *iters, void *work,
+                          size_t work_bytes, int32_t out[2], float *ms, void *stream)
 {
+    clear_error();
     if (path != 0 && path != 1)
         return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
-    int rc = batch_common(cs, code_id, off, llr, F, max_iter, bits, iters, work, work_bytes);
+    int rc = batch_common(cs, code_id, off, llr, n_llr, F, max_iter, bits, iters, work, work_bytes);
     if (rc)
         return rc;
     if (F == 0 || !out || !ms)
         return fail(LDPC_EINVAL, "autotune needs a non-empty batch and output pointers");
-    return codeset_autotune(cs, path, code_id, off, llr, F, max_iter, bits, iters, work, (hipStream_t)stream, out,
-                            ms);
+    return codeset_autotune(cs, path, code_id, off, llr, n_llr, F, max_iter, bits, iters, work, (hipStream_t)stream,
+                            out, ms);
 }
 
 }  // extern "C"

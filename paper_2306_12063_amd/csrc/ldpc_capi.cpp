@@ -470,6 +470,76 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
     return LDPC_OK;
 }
 
+static void layout_row(const DecodeLaunch &lc, int32_t *o)
+{
+    o[0] = lc.G;
+    o[1] = lc.KF;
+    o[2] = lc.FWp;
+    o[3] = lc.threads;
+    o[4] = lc.hoist;
+    o[5] = lc.h2;
+    o[6] = lc.waves;
+}
+
+int ldpc_decode_layouts(const int16_t *hbm, int Mb, int Nb, int Z, int path, int32_t *out, int cap)
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if (path != 0 && path != 1)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (cap < 0 || (cap > 0 && !out))
+        return fail(LDPC_EINVAL, "negative capacity or null output pointer");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "decode layouts need run-time specialised kernels (LDPC_JIT=0 is set)");
+    std::vector<DecodeLaunch> v;
+    if ((rc = tuner_layouts(sc, path, &v, nullptr)))
+        return rc;
+    for (int k = 0; k < (int)v.size() && k < cap; ++k)
+        layout_row(v[k], out + 7 * k);
+    return (int)v.size();
+}
+
+int ldpc_set_decode_layout(const int16_t *hbm, int Mb, int Nb, int Z, int path, const int32_t layout[7])
+{
+    clear_error();
+    Sched sc;
+    int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
+    if (rc)
+        return rc;
+    if (path != 0 && path != 1)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (!jit_enabled())
+        return fail(LDPC_ERANGE, "decode layouts need run-time specialised kernels (LDPC_JIT=0 is set)");
+    if (!layout) {
+        clear_tuned_launch(sc, path);
+        return LDPC_OK;
+    }
+    const int G = layout[0], KF = layout[1], hoist = layout[4], h2 = layout[5], waves = layout[6];
+    if (h2 != 0 && h2 != 1)
+        return fail(LDPC_EINVAL, "packed-FP16 flag must be 0 or 1");
+    if (h2 && (path != 1 || !h2_eligible(sc) || KF != 1))
+        return fail(LDPC_EINVAL, "two frames per lane needs the fixed-point path, KF = 1 and column weight <= 15");
+    DecodeLaunch lc = h2 ? make_h2_launch(sc, G, kMaxThreads) : make_launch(sc, 4, G, KF, kMaxThreads);
+    if (lc.G < 1 || KF < 1 || KF > 2)
+        return fail(LDPC_ERANGE, "layout G=%d KF=%d does not fit this code (threads, LDS or frames per workgroup)", G,
+                    KF);
+    if (layout[2] != lc.FWp || layout[3] != lc.threads)
+        return fail(LDPC_EINVAL, "FWp %d / threads %d do not match G=%d KF=%d (expected %d / %d)", layout[2],
+                    layout[3], G, KF, lc.FWp, lc.threads);
+    if (hoist < 0 || hoist > sc.Mb)
+        return fail(LDPC_EINVAL, "hoisted block rows must be in [0, Mb]");
+    if (waves != 0 && waves != 3 && waves != 4)
+        return fail(LDPC_EINVAL, "waves must be 0, 3 or 4");
+    lc.hoist = hoist;
+    lc.waves = waves;
+    lc.tuned = 1;
+    set_tuned_launch(sc, path, lc);
+    return LDPC_OK;
+}
+
 size_t ldpc_nms_ckpt_bytes(const int16_t *hbm, int Mb, int Nb, int Z, int64_t F, int T)
 {
     clear_error();

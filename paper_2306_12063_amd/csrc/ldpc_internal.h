@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/ldpc.h"
 
@@ -139,6 +140,11 @@ DecodeLaunch make_launch(const Sched &sc, int elem_bytes, int G, int KF, int max
 bool tuned_launch(const Sched &sc, int path, DecodeLaunch *out);
 void set_tuned_launch(const Sched &sc, int path, const DecodeLaunch &lc);
 void tune_cache_clear();
+void clear_tuned_launch(const Sched &sc, int path);
+// Every layout the autotuner times for this code and path, in timing order
+// (compiles each candidate to read its registers and spills); scratch
+// receives each layout's spilled bytes per lane.
+int tuner_layouts(const Sched &sc, int path, std::vector<DecodeLaunch> *out, std::vector<size_t> *scratch);
 // Times candidate layouts of the specialised kernel (jit) on F zero frames.
 int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStream_t stream, DecodeLaunch *best,
                     float *best_ms);

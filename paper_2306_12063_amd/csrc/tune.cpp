@@ -107,18 +107,60 @@ void tune_cache_clear()
     g_tuned.clear();
 }
 
+int tuner_layouts(const Sched &sc, int path, std::vector<DecodeLaunch> *out, std::vector<size_t> *scratch_out)
+{
+    // candidates, then for each one whose kernel holds more than 128 VGPRs
+    // per lane the same layout compiled for one more wave per SIMD (a hint
+    // to the register allocator). Spilled registers live in scratch memory
+    // and add HBM traffic: an unhinted layout that spills is dropped, a
+    // hinted one may spill at most 32 bytes per lane.
+    const char *lv = getenv("LDPC_TUNE_LOG");
+    const bool log = lv && lv[0] == '1';
+    std::vector<DecodeLaunch> work = candidates(sc, 4, path);   // FP32 posteriors in LDS on both paths
+    out->clear();
+    if (scratch_out)
+        scratch_out->clear();
+    for (size_t w = 0; w < work.size(); ++w) {
+        const DecodeLaunch lc = work[w];
+        size_t scratch = 0;
+        int vgprs = 0;
+        int rc = jit_decode_scratch(sc, lc, path, 0, &scratch, &vgprs);
+        if (rc)
+            return rc;
+        const size_t allowed = lc.waves ? 32 : 0;
+        if (scratch > allowed) {
+            if (log)
+                fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d waves %d spills %zu bytes, skipped\n", lc.G,
+                        lc.KF, lc.hoist, lc.waves, scratch);
+            continue;
+        }
+        if (lc.waves == 0 && vgprs > 128) {
+            DecodeLaunch v = lc;
+            v.waves = vgprs > 168 ? 3 : 4;
+            work.push_back(v);
+        }
+        out->push_back(lc);
+        if (scratch_out)
+            scratch_out->push_back(scratch);
+    }
+    return LDPC_OK;
+}
+
 int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStream_t stream, DecodeLaunch *best,
                     float *best_ms)
 {
-    const int eb = 4;   // FP32 posteriors in LDS on both paths
     const size_t in_bytes = (size_t)F * sc.N * (path == 0 ? 4 : 1);
     void *llr = nullptr, *bits = nullptr, *iters = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = LDPC_OK;
     float best_t = 1e30f, spill_t = 1e30f;
     DecodeLaunch best_lc{}, spill_lc{};
+    std::vector<DecodeLaunch> work;
+    std::vector<size_t> spills;
     const char *lv = getenv("LDPC_TUNE_LOG");   // set to 1: print every candidate's time
     const bool log = lv && lv[0] == '1';
+    if ((rc = tuner_layouts(sc, path, &work, &spills)))
+        return rc;
     if (hipMalloc(&llr, in_bytes) != hipSuccess || hipMalloc(&bits, (size_t)F * sc.N) != hipSuccess ||
         hipMalloc(&iters, (size_t)F * sizeof(int32_t)) != hipSuccess) {
         rc = fail(LDPC_ENOMEM, "autotune: device allocation failed");
@@ -129,69 +171,47 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         rc = fail(LDPC_EDEVICE, "autotune: HIP setup failed");
         goto done;
     }
-    {
-        // candidates, then for each one whose kernel holds more than 128
-        // VGPRs per lane the same layout compiled for one more wave per SIMD
-        // (a hint to the register allocator). Spilled registers live in
-        // scratch memory and add HBM traffic, so such a variant may spill at
-        // most 32 bytes per lane and replaces the fastest spill-free layout
-        // only if it is at least 5% faster.
-        std::vector<DecodeLaunch> work = candidates(sc, eb, path);
-        for (size_t w = 0; w < work.size(); ++w) {
-            const DecodeLaunch lc = work[w];
-            size_t scratch = 0;
-            int vgprs = 0;
-            if ((rc = jit_decode_scratch(sc, lc, path, 0, &scratch, &vgprs)))
-                goto done;
-            const size_t allowed = lc.waves ? 32 : 0;
-            if (scratch > allowed) {
-                if (log)
-                    fprintf(stderr, "ldpc autotune: G %d KF %d hoist %d waves %d spills %zu bytes, skipped\n", lc.G,
-                            lc.KF, lc.hoist, lc.waves, scratch);
-                continue;
-            }
-            if (lc.waves == 0 && vgprs > 128) {
-                DecodeLaunch v = lc;
-                v.waves = vgprs > 168 ? 3 : 4;
-                work.push_back(v);
-            }
-            // the first launch warms the caches
+    // a layout that spills replaces the fastest spill-free one only if it is
+    // at least 5% faster
+    for (size_t w = 0; w < work.size(); ++w) {
+        const DecodeLaunch lc = work[w];
+        const size_t scratch = spills[w];
+        // the first launch warms the caches
+        rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr, (uint8_t *)bits,
+                               nullptr, (int32_t *)iters, nullptr, stream);
+        if (rc)
+            goto done;
+        const int reps = 3;
+        hipEventRecord(e0, stream);
+        for (int k = 0; k < reps && rc == LDPC_OK; ++k)
             rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
                                    (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
-            if (rc)
-                goto done;
-            const int reps = 3;
-            hipEventRecord(e0, stream);
-            for (int k = 0; k < reps && rc == LDPC_OK; ++k)
-                rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
-                                       (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
-            hipEventRecord(e1, stream);
-            if (rc)
-                goto done;
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(LDPC_EDEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
-                goto done;
-            }
-            float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
-            ms /= reps;
-            if (log)
-                fprintf(stderr,
-                        "ldpc autotune: path %d Z %d Mb %d  G %d KF %d threads %d hoisted rows %d h2 %d waves %d "
-                        "vgprs %d scratch %zu  %.4f ms\n",
-                        path, sc.Z, sc.Mb, lc.G, lc.KF, lc.threads, lc.hoist, lc.h2, lc.waves, vgprs, scratch, ms);
-            if (scratch == 0 && ms < best_t) {
-                best_t = ms;
-                best_lc = lc;
-            } else if (scratch > 0 && ms < spill_t) {
-                spill_t = ms;
-                spill_lc = lc;
-            }
+        hipEventRecord(e1, stream);
+        if (rc)
+            goto done;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(LDPC_EDEVICE, "autotune: %s", hipGetErrorString(hipGetLastError()));
+            goto done;
         }
-        if (spill_lc.G >= 1 && (best_lc.G < 1 || spill_t < 0.95f * best_t)) {
-            best_t = spill_t;
-            best_lc = spill_lc;
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (log)
+            fprintf(stderr,
+                    "ldpc autotune: path %d Z %d Mb %d  G %d KF %d threads %d hoisted rows %d h2 %d waves %d "
+                    "scratch %zu  %.4f ms\n",
+                    path, sc.Z, sc.Mb, lc.G, lc.KF, lc.threads, lc.hoist, lc.h2, lc.waves, scratch, ms);
+        if (scratch == 0 && ms < best_t) {
+            best_t = ms;
+            best_lc = lc;
+        } else if (scratch > 0 && ms < spill_t) {
+            spill_t = ms;
+            spill_lc = lc;
         }
+    }
+    if (spill_lc.G >= 1 && (best_lc.G < 1 || spill_t < 0.95f * best_t)) {
+        best_t = spill_t;
+        best_lc = spill_lc;
     }
     if (best_lc.G < 1) {
         rc = fail(LDPC_ERANGE, "autotune: no decode layout fits this code");
@@ -213,6 +233,12 @@ done:
     if (iters)
         (void)hipFree(iters);
     return rc;
+}
+
+void clear_tuned_launch(const Sched &sc, int path)
+{
+    std::lock_guard<std::mutex> lock(g_tmu);
+    g_tuned.erase(tune_key(sc, path));
 }
 
 }  // namespace ldpc

@@ -220,7 +220,7 @@ def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, s
     return dict(train_seconds=t_train, loss_first=hist[0], loss_last=float(np.mean(hist[-16:])),
                 train_range=list(train_range), lr=lr, lr_final=lr_final, tie=tie, iter_loss=iter_loss,
                 summary=summary, sweep=res,
-                weights=w.cpu().numpy().round(5).tolist())
+                weights=w.cpu().numpy().round(5).tolist(), w=w)
 
 
 def _code(spec):
@@ -251,6 +251,7 @@ def main():
     r = compare(hbm, Z, args.train_frames, args.eval_frames, pts, args.seed, log_every=64, train_range=(lo, hi),
                 lr=args.lr, lr_final=args.lr_final, tie=args.tie, iter_loss=args.iter_loss)
     r["code"] = args.code
+    r.pop("w")
     print(json.dumps(r), flush=True)
 
 

@@ -180,9 +180,10 @@ def test_batch_autotune_keeps_parity():
 def test_batch_grouping_one_dominant_code(path):
     # Frames of a batch are grouped by code in per-workgroup LDS counts with
     # one global count per code and workgroup: here most of 9000 frames (three
-    # such workgroups) share one code, some carry invalid code ids (their
-    # outputs must stay untouched), and one code has N < 256, so a thread's
-    # share of a work item spans several frames.
+    # such workgroups) share one code, some carry invalid code ids and a few
+    # offsets that would reach outside the buffers (those frames are not
+    # decoded: iters -1, ok 0, bits and posteriors untouched), and one code
+    # has N < 256, so a thread's share of a work item spans several frames.
     codes = [("1/2", 8, synth.wimax_code("1/2", 8, seed=4)), ("5/6", 24, synth.wimax_code("5/6", 24, seed=5)),
              ("3/4A", 52, synth.wimax_code("3/4A", 52, seed=6))]
     cs = P.Codeset([(h, Z) for _, Z, h in codes])
@@ -203,30 +204,42 @@ def test_batch_grouping_one_dominant_code(path):
         for k, f in enumerate(idx):
             llr[off[f]:off[f] + Ns[c]] = l[k]
         per[c] = (idx, l)
+    # frames of valid codes whose offsets leave the buffers (checked on the
+    # device against the element count the binding passes)
+    moved = {}
+    for f, o in zip(per[1][0][[3, 50, 400, 2000, 5000]], (-1, -int(Ns[1]), total - int(Ns[1]) + 1, total, 1 << 40)):
+        moved[int(f)] = int(off[f])
+        off[f] = o
     d = lambda x: torch.from_numpy(x).to(DEV)
     bits = torch.full((total,), 7, dtype=torch.uint8, device=DEV)
     iters = torch.full((F,), -5, dtype=torch.int32, device=DEV)
+    ok = torch.full((F,), 9, dtype=torch.uint8, device=DEV)
     if path == "f32":
         bits, post, iters, ok = cs.decode_f32(d(cid), d(off), d(llr), max_iter=6, alpha=0.75, early_term=True,
-                                              bits=bits, iters=iters)
+                                              bits=bits, iters=iters, ok=ok)
     else:
         bits, post, iters, ok = cs.decode_i8(d(cid), d(off), d(oracle.quantize_i8(llr)), max_iter=6, offset=1,
-                                             early_term=True, bits=bits, iters=iters)
+                                             early_term=True, bits=bits, iters=iters, ok=ok)
     torch.cuda.synchronize()
-    bits, post, iters = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy()
+    bits, post, iters, ok = bits.cpu().numpy(), post.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy()
     for c, (idx, l) in per.items():
         _, Z, h = codes[c]
         if path == "f32":
-            wb, wp, wi, _ = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
+            wb, wp, wi, wo = oracle.decode_f32(h, Z, l, max_iter=6, alpha=0.75, early_term=True)
         else:
-            wb, wp, wi, _ = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=6, offset=1, early_term=True)
+            wb, wp, wi, wo = oracle.decode_i8(h, Z, oracle.quantize_i8(l), max_iter=6, offset=1, early_term=True)
         for k, f in enumerate(idx):
+            if int(f) in moved:
+                continue
             s = slice(off[f], off[f] + Ns[c])
             assert np.array_equal(bits[s], wb[k]) and np.array_equal(post[s], wp[k]) and iters[f] == wi[k], (c, f)
+            assert ok[f] == wo[k]
     bad = np.flatnonzero((cid < 0) | (cid >= 3))
     assert len(bad) > 0
     for f in bad:
-        assert iters[f] == -5 and np.all(bits[off[f]:off[f] + 16] == 7)
+        assert iters[f] == -1 and ok[f] == 0 and np.all(bits[off[f]:off[f] + 16] == 7)
+    for f, o in moved.items():
+        assert iters[f] == -1 and ok[f] == 0 and np.all(bits[o:o + Ns[1]] == 7), f
 
 
 @pytest.mark.parametrize("packed", [True, False])
