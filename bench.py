@@ -114,6 +114,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """One line on stderr as each stage of the benchmark ends."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def source_sha(*names):
     h = hashlib.sha256()
     for n in names:
@@ -209,7 +214,9 @@ def cpu_baseline(sets):
                 for k, v in per.items()}, wall
 
     one, w1 = run(1)
+    progress(f"CPU oracle, one thread: {w1:.1f} s")
     many, wn = run(threads)
+    progress(f"CPU oracle, {threads} threads: {wn:.1f} s")
     flags = " ".join(oracle.build.FLAGS)
     c2n = next(st for st in sets if st["name"] == "C2")
     return {"value": many["C2"]["gbit_s"], "unit": "Gbit/s", "cores": threads, "kind": "oracle",
@@ -484,6 +491,7 @@ def learned_gain(train_frames, eval_frames, parity=True):
         r = learned.compare(hbm, Zl, train_frames=train_frames, eval_frames=eval_frames, ebn0_list=pts, seed=1,
                             train_range=tr, lr=1e-2, lr_final=1e-3)
         sm = r["summary"]
+        progress(f"learned {name}: trained and evaluated")
         par = _learned_parity(hbm, Zl, r["w"], pts[len(pts) // 2]) if parity else None
         out[name] = {
             "workload": f"{what}, Z={Zl} (N={hbm.shape[1] * Zl}); training on {train_frames} fresh frames "
@@ -571,6 +579,7 @@ def main():
             cfg = P.ldpc_autotune_decode(c["hbm"], Z, path=c["path"], max_iter=ITERS, F=min(F, 16384))
             layouts[f"{c['path']} {c['rate']}"] = {k: cfg[k] for k in ("G", "KF", "threads", "hoist", "h2", "waves")}
     torch.cuda.synchronize()
+    progress("frames generated, decode layouts tuned")
 
     def launch(c):
         if c["path"] == "f32":
@@ -598,6 +607,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    progress(f"timed region: {wall:.3f} s")
     info_bits = args.steps * sum(F * c["K"] for c in cases)
     value = info_bits / wall / 1e9
     sha = source_sha("jit_decode.hip", "jit_h2.hip", "jit.cpp")
@@ -639,6 +649,8 @@ def main():
             parity["per_case"][f"{c['path']} {c['rate']}"] = bad
             parity["frames"] += len(idx)
             parity["mismatches"] += bad
+
+        progress(f"oracle parity of the timed launches: {parity['mismatches']} of {parity['frames']} frames differ")
 
     # Secondary, untimed in the headline: the same launches writing their
     # posteriors too (ldpc_decode_* specify them; the paper's throughput counts
@@ -711,14 +723,17 @@ def main():
                                                cpu_frames=0 if args.no_cpu_baseline else args.cpu_frames)
         if host is not None:
             cpu_sets.append(host)
+        progress("mixed batch done")
     if not args.no_sweep:
         out["et_sweep"] = et_sweep(P, torch, dev, F)
         host, out["small_code"] = small_code(P, torch, dev)
+        progress("early-termination sweep and small code done")
         if not args.no_cpu_baseline:
             cpu_sets.append(host)
     if not args.no_learned:
         out["learned"] = learned_gain(args.learned_train_frames, args.learned_eval_frames,
                                       parity=not args.no_parity)
+        progress("learned-versus-plain comparison done")
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -91,6 +91,11 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"libldpc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+            # torch ships its own HIP runtime under the same soname; loading
+            # it first makes the library bind to that one copy. Opened the
+            # other way round, the process would hold two HIP runtimes and
+            # device pointers from torch would be foreign to the library.
+            _torch()
             L = C.CDLL(LIB_PATH)
             for name, (args, res) in EXPORTS.items():
                 fn = getattr(L, name)
