@@ -344,6 +344,25 @@ int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const i
                          int16_t *post, int32_t *iters, uint8_t *ok, void *work, size_t work_bytes, void *stream);
 
 /*
+ * Allocation-free batched FP32 decode, for callers that cannot allocate
+ * device memory during a call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation). Arguments, arithmetic and
+ * outputs as ldpc_decode_batch_f32, without the work buffer: the work list
+ * lives in a static device array of the library, one per GPU, kept until
+ * the process ends, with room for F <= 262144 frames (LDPC_ERANGE beyond).
+ * The call allocates nothing and loads no kernel: the code set's batch
+ * kernels for the FP32 path at its current layout must already be loaded on
+ * this device by an earlier ldpc_decode_batch_f32 or ldpc_codeset_autotune
+ * call (FP32), else LDPC_ERANGE. Every call on one GPU shares the one array:
+ * calls that overlap on a GPU (on different streams, or from several host
+ * threads) race and must be ordered by the caller.
+ */
+int ldpc_decode_batch_f32_noalloc(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off,
+                                  const float *llr, int64_t n_llr, int64_t F, int max_iter, float alpha,
+                                  int early_term, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok,
+                                  void *stream);
+
+/*
  * Batch layout autotuner (frames per work item and workgroup size of the
  * persistent kernel). Decodes the caller's batch -- same arguments as
  * ldpc_decode_batch_f32/_i8 for `path` 0/1 -- with alpha 0.75 (FP32) or

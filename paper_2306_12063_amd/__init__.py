@@ -57,6 +57,7 @@ EXPORTS = {
                               _i32),
     "ldpc_decode_batch_i8": ([_p, _p, _p, _p, _i64, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, C.c_size_t,
                               _p], _i32),
+    "ldpc_decode_batch_f32_noalloc": ([_p, _p, _p, _p, _i64, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p], _i32),
     "ldpc_codeset_set_layout": ([_p, _i32, _i32, _i32], _i32),
     "ldpc_decode_layouts": ([_p, _i32, _i32, _i32, _i32, _p, _i32], _i32),
     "ldpc_set_decode_layout": ([_p, _i32, _i32, _i32, _i32, _p], _i32),
@@ -619,6 +620,22 @@ class Codeset:
         return self._decode("ldpc_decode_batch_f32", code_id, off, llr, llr.numel(), code_id.numel(),
                             (int(max_iter), float(alpha), int(bool(early_term))), bits, post, iters, ok, work, stream,
                             torch.float32, torch.float32, want_post)
+
+    def decode_f32_noalloc(self, code_id, off, llr, bits, iters, post=None, ok=None, max_iter=10, alpha=0.75,
+                           early_term=True, stream=None):
+        """ldpc_decode_batch_f32_noalloc: as decode_f32, into the caller's
+        output tensors (bits, iters; post and ok optional), with the work list
+        in the library's static device scratch; neither the binding nor the
+        library allocates device memory."""
+        torch = _torch()
+        F, total = code_id.numel(), llr.numel()
+        _check(lib().ldpc_decode_batch_f32_noalloc(
+            self._cs, _dev(code_id, torch.int32, "code_id", (F,)), _dev(off, torch.int64, "off", (F,)),
+            _dev(llr, torch.float32, "llr", (total,)), total, F, int(max_iter), float(alpha), int(bool(early_term)),
+            _dev(bits, torch.uint8, "bits", (total,)), _opt(post, torch.float32, "post", (total,)),
+            _dev(iters, torch.int32, "iters", (F,)), _opt(ok, torch.uint8, "ok", (F,)), _stream(stream)),
+            "ldpc_decode_batch_f32_noalloc")
+        return bits, post, iters, ok
 
     def autotune(self, path, code_id, off, llr, max_iter=10, work=None, stream=None):
         """Times the batch layouts on this batch (ldpc_codeset_autotune) and keeps

@@ -52,7 +52,8 @@ def _units():
              ("batch.cpp", [], "batch.o"),
              (os.path.join(OBJ, "jit_source.cpp"), [], "jit_source.o"),
              ("decode_dispatch.cpp", [], "decode_dispatch.o"),
-             ("frame_kernels.hip", [], "frame_kernels.o")]
+             ("frame_kernels.hip", [], "frame_kernels.o"),
+             ("batch_scratch.hip", [], "batch_scratch.o")]
     for kind in ("f32", "i8"):
         for mb, d in SHAPES:
             units.append((f"decode_{kind}.hip", [f"-DLDPC_MB={mb}", f"-DLDPC_D={d}"],

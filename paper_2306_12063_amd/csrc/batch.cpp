@@ -247,18 +247,21 @@ size_t batch_work_bytes(const ldpc_codeset *cs, int64_t F)
 int launch_batch_decode(const ldpc_codeset *cs, int path, int mode, const int32_t *code_id, const int64_t *off,
                         const void *llr, int64_t n_llr, int64_t F, int max_iter, float alpha, int offset, int wq,
                         int et, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, void *work,
-                        hipStream_t stream)
+                        hipStream_t stream, bool loaded_only)
 {
     const std::string pre = batch_prelude(*cs, path, mode);
-    hipFunction_t f_clear, f_hist, f_plan, f_items, f_scatter, f_dec;
+    static const char *const names[6] = {"ldpc_batch_clear", "ldpc_batch_hist",    "ldpc_batch_plan",
+                                         "ldpc_batch_items", "ldpc_batch_scatter", "ldpc_batch_decode"};
+    hipFunction_t fn[6];
     int rc;
-    if ((rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_clear", &f_clear)) ||
-        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_hist", &f_hist)) ||
-        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_plan", &f_plan)) ||
-        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_items", &f_items)) ||
-        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_scatter", &f_scatter)) ||
-        (rc = jit_function("batch", kJitBatchSource, pre, "ldpc_batch_decode", &f_dec)))
-        return rc;
+    for (int k = 0; k < 6; ++k) {
+        rc = loaded_only ? jit_function_loaded("batch", pre, names[k], &fn[k])
+                         : jit_function("batch", kJitBatchSource, pre, names[k], &fn[k]);
+        if (rc)
+            return rc;
+    }
+    hipFunction_t f_clear = fn[0], f_hist = fn[1], f_plan = fn[2], f_items = fn[3], f_scatter = fn[4],
+                  f_dec = fn[5];
     const int64_t hw = head_words(cs->ncodes);
     int64_t *head = (int64_t *)work;
     int64_t *perm = head + hw;
@@ -326,7 +329,7 @@ int codeset_autotune(ldpc_codeset *cs, int path, const int32_t *code_id, const i
             break;
         auto run = [&]() {
             return launch_batch_decode(cs, path, 0, code_id, off, llr, n_llr, F, max_iter, 0.75f, 1, 0, 0, bits,
-                                       nullptr, iters, nullptr, work, stream);
+                                       nullptr, iters, nullptr, work, stream, false);
         };
         if ((rc = run()))   // compiles the variant and warms the caches
             break;
@@ -445,7 +448,37 @@ int ldpc_decode_batch_f32(const ldpc_codeset *cs, const int32_t *code_id, const 
     if (rc || F == 0)
         return rc;
     return launch_batch_decode(cs, 0, 0, code_id, off, llr, n_llr, F, max_iter, alpha, 0, 0, early_term, bits, post,
-                               iters, ok, work, (hipStream_t)stream);
+                               iters, ok, work, (hipStream_t)stream, false);
+}
+
+int ldpc_decode_batch_f32_noalloc(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off,
+                                  const float *llr, int64_t n_llr, int64_t F, int max_iter, float alpha,
+                                  int early_term, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok,
+                                  void *stream)
+{
+    clear_error();
+    if (!cs)
+        return fail(LDPC_EINVAL, "null code set");
+    // the scratch is sized for kBatchScratchFrames frames of a 1024-code set
+    if (F > kBatchScratchFrames || (F > 0 && batch_work_bytes(cs, F) > kBatchScratchBytes))
+        return fail(LDPC_ERANGE, "%lld frames exceed the static scratch (at most %d frames)", (long long)F,
+                    kBatchScratchFrames);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipGetDevice failed");
+    void *scratch = nullptr;
+    int rc = batch_scratch(dev, &scratch);
+    if (rc)
+        return rc;
+    rc = batch_common(cs, code_id, off, llr, n_llr, F, max_iter, bits, iters, scratch, kBatchScratchBytes);
+    if (rc || F == 0)
+        return rc;
+    rc = launch_batch_decode(cs, 0, 0, code_id, off, llr, n_llr, F, max_iter, alpha, 0, 0, early_term, bits, post,
+                             iters, ok, scratch, (hipStream_t)stream, true);
+    if (rc == LDPC_ERANGE)
+        return fail(LDPC_ERANGE, "the batch kernels of this code set are not loaded on device %d: make one "
+                    "ldpc_decode_batch_f32 or ldpc_codeset_autotune call (FP32) with it first", dev);
+    return rc;
 }
 
 int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const int64_t *off, const int8_t *llr,
@@ -458,7 +491,7 @@ int ldpc_decode_batch_i8(const ldpc_codeset *cs, const int32_t *code_id, const i
     if (offset < 0 || offset > 127 || wq < 0 || wq > 31)
         return fail(LDPC_EINVAL, "offset must be in [0, 127] and wq in [0, 31]");
     return launch_batch_decode(cs, 1, wq > 0 ? 1 : 0, code_id, off, llr, n_llr, F, max_iter, 0.0f, offset, wq,
-                               early_term, bits, post, iters, ok, work, (hipStream_t)stream);
+                               early_term, bits, post, iters, ok, work, (hipStream_t)stream, false);
 }
 
 int ldpc_codeset_set_layout(ldpc_codeset *cs, int path, int threads, int divisor)

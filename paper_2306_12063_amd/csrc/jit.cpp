@@ -222,6 +222,25 @@ int jit_function(const char *tag, const char *src, const std::string &pre, const
     return get_function(tag, src, pre, name, fn);
 }
 
+int jit_function_loaded(const char *tag, const std::string &pre, const char *name, hipFunction_t *fn)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipGetDevice failed");
+    const std::string key = std::to_string(dev) + "\n" + tag + "\n" + pre;
+    hipModule_t mod;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_cache.find(key);
+        if (it == g_cache.end())
+            return fail(LDPC_ERANGE, "kernel %s is not loaded on device %d yet", name, dev);
+        mod = it->second.mod;
+    }
+    if (hipModuleGetFunction(fn, mod, name) != hipSuccess)
+        return fail(LDPC_EDEVICE, "hipModuleGetFunction(%s) failed", name);
+    return LDPC_OK;
+}
+
 int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what)
 {
     return launch(fn, blocks, threads, stream, args, what);

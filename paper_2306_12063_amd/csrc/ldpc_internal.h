@@ -101,6 +101,21 @@ bool jit_enabled();
 void jit_cache_clear();
 // Function `name` of the module built from prelude + source (cached per device).
 int jit_function(const char *tag, const char *src, const std::string &pre, const char *name, hipFunction_t *fn);
+// Static scratch of ldpc_decode_batch_f32_noalloc: the batched decode's
+// work list for up to kBatchScratchFrames frames of a code set of up to 1024
+// codes (2 + 3 * 1024 queue words, then 32 bytes per frame and 16 per code).
+constexpr int kBatchScratchFrames = 1 << 18;
+constexpr size_t kBatchScratchBytes =
+    ((size_t)(3074 + 2 * (size_t)kBatchScratchFrames) * 8 + ((size_t)kBatchScratchFrames + 1024) * 16 + 255) &
+    ~(size_t)255;
+// Device address of the static scratch on device `dev` (which must be
+// current): looked up once per device, then cached.
+int batch_scratch(int dev, void **out);
+
+// As jit_function, but only finds a kernel whose module this process has
+// already loaded on the current device; never compiles or loads a module
+// (LDPC_ERANGE if it is not loaded).
+int jit_function_loaded(const char *tag, const std::string &pre, const char *name, hipFunction_t *fn);
 int jit_launch(hipFunction_t fn, unsigned blocks, unsigned threads, hipStream_t stream, void **args, const char *what);
 // Default run-time specialised decode layout: one frame per thread (each
 // thread keeps one FP32 message per edge of its check rows), gather

@@ -97,6 +97,9 @@ def test_null_device_pointers_rejected():
     rc = P.lib().ldpc_decode_i8(h.ctypes.data_as(C.c_void_p), 12, 24, 27, None, 5, 10, 200, 0, None, 1,
                                 None, None, None, None, None)
     assert rc == P.LDPC_EINVAL and "offset" in P.ldpc_last_error()
+    rc = P.lib().ldpc_decode_batch_f32_noalloc(None, None, None, None, 0, 5, 10, 0.75, 1, None, None, None, None,
+                                               None)
+    assert rc == P.LDPC_EINVAL and "null code set" in P.ldpc_last_error()
 
 
 def test_encoder_structure_rejected_without_gpu():
