@@ -10,12 +10,14 @@
 // at PAD + n*FWP + p holds frames 2p, 2p+1), the message of every edge of
 // the thread's rows, and all per-edge arithmetic, which is the update of
 // jit_decode.hip on pairs:
-//   Q = L - R (v_pk_add_f16);  |Q| = Q & 0x7fff7fff;  min1/min2 as unsigned
-//   16-bit min/max of the magnitudes' bit patterns (non-negative FP16 values
-//   order as their bits);  sign parity = XOR of the Q words (bits 15, 31);
-//   magnitude = |Q| == min1 ? n2 : n1 as n2 + min(|Q| - min1, 1) * (n1 - n2)
-//   on 16-bit lanes (v_pk_mad_u16);  R = (Q & 0x80008000) ^ magnitude (the
-//   parity is in the magnitude's sign bits);  L = Q + R (v_pk_add_f16).
+//   Q = L - R (v_pk_add_f16);  |Q| = Q & 0x7fff7fff;  min1/min2 by
+//   three-input IEEE minimum/maximum (v_pk_minimum3_f16 / _maximum3_f16),
+//   two edges per step;  sign parity = XOR of the Q words (bits 15, 31);
+//   u = clamp(min1 + 1 - |Q|, 0, 1), which is 1 where |Q| == min1 and 0
+//   elsewhere because every value is an integer (one v_pk_add_f16 with
+//   clamp);  magnitude = u * (n2s - n1s) + n1s (v_pk_fma_f16, exact), with
+//   n1s, n2s the row's two magnitudes carrying the parity in their sign
+//   bits;  R = (Q & 0x80008000) ^ magnitude;  L = Q + R (v_pk_add_f16).
 // A frame that stops (early termination) has its outputs written at once;
 // its half of the pair then keeps being updated but is no longer tested or
 // written, so the per-edge work needs no mask. Per-row magnitude rules (offset, or wq/16 in
@@ -156,8 +158,6 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
 #pragma unroll
     for (int e = 0; e < ED; ++e)
         R[e] = 0u;
-    u32 one = 0x00010001u;
-    asm volatile("" : "+v"(one));   // keeps min(d, 1) * D as a multiply-add
     const u32 beta = W((h2){(_Float16)(float)offset, (_Float16)(float)offset});
     const float wqf = (float)wq;
     __syncthreads();
@@ -212,44 +212,50 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                     ix[e] = gather_b(i, e, rr, rbn, rbw);
                     Q[e] = W(H(ldb(Ls, ix[e])) - H(R[eo + e]));
                 }
-                u2 m1 = {0x7fff, 0x7fff}, m2 = m1;
+                // magnitudes; min1/min2 by IEEE minimum/maximum (no NaN,
+                // no -0: non-negative values), two edges at a time
+                h2 A[MAXD];
 #pragma unroll
-                for (int e = 0; e < d; ++e) {
-                    const u2 a = V(Q[e] & 0x7fff7fffu);
-                    m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, a));
-                    m1 = __builtin_elementwise_min(m1, a);
+                for (int e = 0; e < d; ++e)
+                    A[e] = H(Q[e] & 0x7fff7fffu);
+                h2 m1 = __builtin_elementwise_minimum(A[0], A[1]);
+                h2 m2 = __builtin_elementwise_maximum(A[0], A[1]);
+#pragma unroll
+                for (int e = 2; e + 1 < d; e += 2) {
+                    const h2 lo = __builtin_elementwise_minimum(A[e], A[e + 1]);
+                    const h2 hi = __builtin_elementwise_maximum(A[e], A[e + 1]);
+                    m2 = __builtin_elementwise_minimum(__builtin_elementwise_minimum(m2, hi),
+                                                       __builtin_elementwise_maximum(m1, lo));
+                    m1 = __builtin_elementwise_minimum(m1, lo);
+                }
+                if constexpr (d % 2 == 1) {
+                    m2 = __builtin_elementwise_minimum(m2, __builtin_elementwise_maximum(m1, A[d - 1]));
+                    m1 = __builtin_elementwise_minimum(m1, A[d - 1]);
                 }
                 const u32 par = xor_bits<d>(Q) & 0x80008000u;
-                const u2 cap = {0x57f0, 0x57f0};   // 127.0 in FP16
-                const u32 c1 = W(__builtin_elementwise_min(m1, cap)), c2 = W(__builtin_elementwise_min(m2, cap));
-                u32 n1, n2;
+                const h2 cap = {(_Float16)127.0f, (_Float16)127.0f};
+                const h2 c1 = __builtin_elementwise_minimum(m1, cap), c2 = __builtin_elementwise_minimum(m2, cap);
+                h2 n1, n2;
 #if LDPC_MODE == 0
                 {
-                    // max(c - offset, 0): negative FP16 values are negative as int16
-                    typedef short s2 __attribute__((ext_vector_type(2)));
-                    const s2 z = {0, 0};
-                    n1 = __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s2, W(H(c1) - H(beta))), z));
-                    n2 = __builtin_bit_cast(u32, __builtin_elementwise_max(__builtin_bit_cast(s2, W(H(c2) - H(beta))), z));
+                    const h2 z = {(_Float16)0.0f, (_Float16)0.0f};
+                    n1 = __builtin_elementwise_maximum(c1 - H(beta), z);
+                    n2 = __builtin_elementwise_maximum(c2 - H(beta), z);
                 }
 #else
-                {
-                    const h2 a1 = H(c1), a2 = H(c2);
-                    const h2 b1 = {(_Float16)norm_mag(wqf, (float)a1.x), (_Float16)norm_mag(wqf, (float)a1.y)};
-                    const h2 b2 = {(_Float16)norm_mag(wqf, (float)a2.x), (_Float16)norm_mag(wqf, (float)a2.y)};
-                    n1 = W(b1);
-                    n2 = W(b2);
-                }
+                n1 = (h2){(_Float16)norm_mag(wqf, (float)c1.x), (_Float16)norm_mag(wqf, (float)c1.y)};
+                n2 = (h2){(_Float16)norm_mag(wqf, (float)c2.x), (_Float16)norm_mag(wqf, (float)c2.y)};
 #endif
-                u32 n2p = n2 | par;
-                u32 dlt = W(V(n1 | par) - V(n2p));
-                asm volatile("" : "+v"(n2p), "+v"(dlt));
+                // the parity in the magnitudes' sign bits; n2s - n1s is exact
+                // (integers below 128 of one sign)
+                const h2 n1s = H(W(n1) | par), dl = H(W(n2) | par) - n1s;
+                const h2 one_h = {(_Float16)1.0f, (_Float16)1.0f}, zero_h = {(_Float16)0.0f, (_Float16)0.0f};
+                const h2 m1p1 = m1 + one_h;
                 u32 bad = 0, hw = 0;
 #pragma unroll
                 for (int e = 0; e < d; ++e) {
-                    const u2 a = V(Q[e] & 0x7fff7fffu);
-                    const u2 c = __builtin_elementwise_min(a - m1, V(one));        // 0 at the minimum, else 1
-                    const u32 mag = W(c * V(dlt) + V(n2p));                        // n2p or n1p
-                    const u32 rv = (Q[e] & 0x80008000u) ^ mag;
+                    const h2 u = __builtin_elementwise_min(__builtin_elementwise_max(m1p1 - A[e], zero_h), one_h);
+                    const u32 rv = (Q[e] & 0x80008000u) ^ W(__builtin_elementwise_fma(u, dl, n1s));
                     R[eo + e] = rv;
                     const u32 lv = W(H(Q[e]) + H(rv));
                     stb(Ls, ix[e], lv);
