@@ -249,9 +249,12 @@ int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, i
  * Seeded information bits from Philox4x32-10 (Salmon et al., SC'11):
  * bit k of frame f is bit (k mod 32) of word (k/32 mod 4) of
  * Philox(counter = {k/128, f, 0, 0}, key = {seed low, seed high}).
+ *   seed_dev : nullable device u64 [1]; when given, the kernel reads the
+ *              seed from it instead of `seed` (so that a captured graph can
+ *              be replayed with a new seed written to that buffer)
  *   info : device u8 [F][K]
  */
-int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream);
+int ldpc_random_bits(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t K, uint8_t *info, void *stream);
 
 /*
  * BPSK over AWGN and the channel LLR (eqs. 16-17):
@@ -260,12 +263,13 @@ int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *s
  * normal from Box-Muller on Philox(counter = {n/4, f, 1, 0}, key = seed):
  * words (2p, 2p+1) with p = (n mod 4)/2 give u = ((word >> 8) + 1/2) 2^-24,
  * z = sqrt(-2 ln u_a) * (cos for even n, sin for odd n)(2 pi u_b).
+ *   seed_dev : nullable device u64 [1] that replaces `seed` when given
  *   cw  : device u8 [F][N] codeword bits,  llr : device f32 [F][N]
  *   sigma_f, scale_f : nullable device f32 [F]; when given (both), frame f
  *         uses sigma_f[f] and scale_f[f] instead of sigma and scale
  */
-int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale,
-                  const float *sigma_f, const float *scale_f, float *llr, void *stream);
+int ldpc_awgn_llr(uint64_t seed, const uint64_t *seed_dev, const uint8_t *cw, int64_t F, int64_t N, float sigma,
+                  float scale, const float *sigma_f, const float *scale_f, float *llr, void *stream);
 
 /*
  * Decoding statistics against the transmitted information bits (the first K

@@ -37,8 +37,8 @@ EXPORTS = {
     "ldpc_encode": ([_p, _i32, _i32, _i32, _p, _p, _i64, _p], _i32),
     "ldpc_decode_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _i32, _p, _p, _p, _p, _p, _p], _i32),
     "ldpc_decode_i8": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p], _i32),
-    "ldpc_random_bits": ([_u64, _i64, _i64, _p, _p], _i32),
-    "ldpc_awgn_llr": ([_u64, _p, _i64, _i64, _f32, _f32, _p, _p, _p, _p], _i32),
+    "ldpc_random_bits": ([_u64, _p, _i64, _i64, _p, _p], _i32),
+    "ldpc_awgn_llr": ([_u64, _p, _p, _i64, _i64, _f32, _f32, _p, _p, _p, _p], _i32),
     "ldpc_frame_stats": ([_p, _p, _p, _p, _i64, _i64, _i64, _p, _p], _i32),
     "ldpc_lds_probe": ([_i32, _i32, _p, _p], _i32),
     "ldpc_fallback_f32": ([_p, _i32, _i32, _i32, _p, _i64, _i32, _f32, _p, _p, _p, _p, _p, _p], _i32),
@@ -438,17 +438,30 @@ def ldpc_quantize_weights(w, out=None, stream=None):
     return out
 
 
+def _seed(seed):
+    """(host seed, device seed address): `seed` is an int, or a GPU int64
+    tensor of one element whose bits the kernel reads as the u64 seed."""
+    torch = _torch()
+    if isinstance(seed, torch.Tensor):
+        return 0, _dev(seed, torch.int64, "seed", (1,))
+    return int(seed) & 0xFFFFFFFFFFFFFFFF, None
+
+
 def ldpc_random_bits(seed, F, K, out=None, device="cuda", stream=None):
+    """Seeded information bits [F][K]; seed is an int or a one-element GPU
+    int64 tensor read by the kernel (graph replays with new seeds)."""
     torch = _torch()
     out = torch.empty((F, K), dtype=torch.uint8, device=device) if out is None else out
-    _check(lib().ldpc_random_bits(int(seed), F, K, _dev(out, torch.uint8, "info", (F, K)), _stream(stream)),
+    hs, ds = _seed(seed)
+    _check(lib().ldpc_random_bits(hs, ds, F, K, _dev(out, torch.uint8, "info", (F, K)), _stream(stream)),
            "ldpc_random_bits")
     return out
 
 
 def ldpc_awgn_llr(seed, cw, sigma, scale, out=None, stream=None):
     """BPSK/AWGN channel LLRs for codewords cw [F][N]. sigma and scale are
-    floats, or GPU float32 tensors [F] of per-frame values."""
+    floats, or GPU float32 tensors [F] of per-frame values; seed as for
+    ldpc_random_bits."""
     torch = _torch()
     F, N = cw.shape
     out = torch.empty((F, N), dtype=torch.float32, device=cw.device) if out is None else out
@@ -456,7 +469,8 @@ def ldpc_awgn_llr(seed, cw, sigma, scale, out=None, stream=None):
     if isinstance(sigma, torch.Tensor):
         sf, cf = _dev(sigma, torch.float32, "sigma", (F,)), _dev(scale, torch.float32, "scale", (F,))
         sigma = scale = 0.0
-    _check(lib().ldpc_awgn_llr(int(seed), _dev(cw, torch.uint8, "cw", (F, N)), F, N, float(sigma), float(scale),
+    hs, ds = _seed(seed)
+    _check(lib().ldpc_awgn_llr(hs, ds, _dev(cw, torch.uint8, "cw", (F, N)), F, N, float(sigma), float(scale),
                                sf, cf, _dev(out, torch.float32, "llr", (F, N)), _stream(stream)), "ldpc_awgn_llr")
     return out
 

@@ -27,8 +27,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k)
 
 // Bit k of frame f = bit (k % 32) of word (k / 32 % 4) of
 // Philox({k / 128, f, 0, 0}, seed). One thread per 128-bit block.
-__global__ void k_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *__restrict__ out)
+__global__ void k_random_bits(uint64_t seed, const uint64_t *__restrict__ seed_dev, int64_t F, int64_t K,
+                              uint8_t *__restrict__ out)
 {
+    if (seed_dev)
+        seed = *seed_dev;
     const int64_t blocks_per_frame = (K + 127) / 128;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= F * blocks_per_frame)
@@ -47,10 +50,13 @@ __global__ void k_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *__re
 // Philox({n / 4, f, 1, 0}, seed), with u = ((word >> 8) + 1/2) 2^-24;
 // cos for even n, sin for odd n. LLR = ((1 - 2x) + sigma z) * scale, in FP32
 // without fused multiply-add. One thread per 4 consecutive positions.
-__global__ void k_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *__restrict__ cw, float sigma,
-                           float scale, const float *__restrict__ sigma_f, const float *__restrict__ scale_f,
+__global__ void k_awgn_llr(uint64_t seed, const uint64_t *__restrict__ seed_dev, int64_t F, int64_t N,
+                           const uint8_t *__restrict__ cw, float sigma, float scale,
+                           const float *__restrict__ sigma_f, const float *__restrict__ scale_f,
                            float *__restrict__ llr)
 {
+    if (seed_dev)
+        seed = *seed_dev;
     const int64_t quads = (N + 3) / 4;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= F * quads)
@@ -279,19 +285,20 @@ int launch_quantize_q16(const float *llr, int16_t *q, int64_t n, float scale, in
     return check_launch(__func__);
 }
 
-int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream)
+int launch_random_bits(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t K, uint8_t *info,
+                       hipStream_t stream)
 {
     const int64_t work = F * ((K + 127) / 128);
-    hipLaunchKernelGGL(k_random_bits, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, F, K, info);
+    hipLaunchKernelGGL(k_random_bits, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, seed_dev, F, K, info);
     return check_launch(__func__);
 }
 
-int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
-                    const float *sigma_f, const float *scale_f, float *llr, hipStream_t stream)
+int launch_awgn_llr(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t N, const uint8_t *cw, float sigma,
+                    float scale, const float *sigma_f, const float *scale_f, float *llr, hipStream_t stream)
 {
     const int64_t work = F * ((N + 3) / 4);
-    hipLaunchKernelGGL(k_awgn_llr, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, F, N, cw, sigma, scale,
-                       sigma_f, scale_f, llr);
+    hipLaunchKernelGGL(k_awgn_llr, dim3(grid_for(work, 256)), dim3(256), 0, stream, seed, seed_dev, F, N, cw, sigma,
+                       scale, sigma_f, scale_f, llr);
     return check_launch(__func__);
 }
 

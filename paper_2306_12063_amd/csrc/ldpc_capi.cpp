@@ -588,7 +588,7 @@ int ldpc_nms_bwd(const int16_t *hbm, int Mb, int Nb, int Z, const uint8_t *cw, i
     return launch_nms_bwd(sc, cw, F, T, w, (float *)ckpt, dloss, grad_w, (hipStream_t)stream);
 }
 
-int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *stream)
+int ldpc_random_bits(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t K, uint8_t *info, void *stream)
 {
     clear_error();
     if (F < 0 || K < 0)
@@ -597,11 +597,11 @@ int ldpc_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, void *s
         return LDPC_OK;
     if (!info)
         return fail(LDPC_EINVAL, "null device pointer");
-    return device_status(launch_random_bits(seed, F, K, info, (hipStream_t)stream), "ldpc_random_bits");
+    return device_status(launch_random_bits(seed, seed_dev, F, K, info, (hipStream_t)stream), "ldpc_random_bits");
 }
 
-int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float sigma, float scale,
-                  const float *sigma_f, const float *scale_f, float *llr, void *stream)
+int ldpc_awgn_llr(uint64_t seed, const uint64_t *seed_dev, const uint8_t *cw, int64_t F, int64_t N, float sigma,
+                  float scale, const float *sigma_f, const float *scale_f, float *llr, void *stream)
 {
     clear_error();
     if (F < 0 || N < 0)
@@ -614,7 +614,8 @@ int ldpc_awgn_llr(uint64_t seed, const uint8_t *cw, int64_t F, int64_t N, float 
         return fail(LDPC_ERANGE, "frame length too large for the noise counter");
     if ((sigma_f == nullptr) != (scale_f == nullptr))
         return fail(LDPC_EINVAL, "per-frame sigma and scale must be given together");
-    return device_status(launch_awgn_llr(seed, F, N, cw, sigma, scale, sigma_f, scale_f, llr, (hipStream_t)stream),
+    return device_status(launch_awgn_llr(seed, seed_dev, F, N, cw, sigma, scale, sigma_f, scale_f, llr,
+                                         (hipStream_t)stream),
                          "ldpc_awgn_llr");
 }
 

@@ -87,8 +87,9 @@ int launch_quantize_weights(const float *w, uint8_t *wq, int64_t n, hipStream_t 
 int launch_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, hipStream_t stream);
 int launch_encode_packed(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
 int launch_encode(const Sched &sc, const uint8_t *info, uint8_t *cw, int64_t F, hipStream_t stream);
-int launch_random_bits(uint64_t seed, int64_t F, int64_t K, uint8_t *info, hipStream_t stream);
-int launch_awgn_llr(uint64_t seed, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
+int launch_random_bits(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t K, uint8_t *info,
+                       hipStream_t stream);
+int launch_awgn_llr(uint64_t seed, const uint64_t *seed_dev, int64_t F, int64_t N, const uint8_t *cw, float sigma, float scale,
                     const float *sigma_f, const float *scale_f, float *llr, hipStream_t stream);
 int launch_frame_stats(const uint8_t *bits, const uint8_t *info, const int32_t *iters, const uint8_t *ok, int64_t F,
                        int64_t N, int64_t K, int64_t *counters, hipStream_t stream);

@@ -106,7 +106,8 @@ def train(hbm, Z, T=10, frames=1 << 20, batch=4096, lr=1e-2, ebn0_range=(1.0, 4.
 
 
 class _Dec:
-    """One decoder form of the comparison."""
+    """One decoder form of the comparison: run(llr, q, bits, iters, ok)
+    decodes into the given buffers, fallback(...) re-decodes failed frames."""
 
     def __init__(self, name, run, fallback):
         self.name, self.run, self.fallback = name, run, fallback
@@ -117,61 +118,174 @@ def decoders(hbm, Z, w, T=10):
     each falls back to plain min-sum with 20 iterations for failed frames."""
     wq = quantize_weights(w)
 
-    def plain(llr, q):
-        return ldpc_decode_f32(hbm, Z, llr, max_iter=T, alpha=0.75, early_term=True, want_post=False)
+    def plain(llr, q, bits, iters, ok):
+        ldpc_decode_f32(hbm, Z, llr, max_iter=T, alpha=0.75, early_term=True, bits=bits, iters=iters, ok=ok,
+                        want_post=False)
 
-    def learned(llr, q):
-        return ldpc_decode_f32(hbm, Z, llr, max_iter=T, w=w, early_term=True, want_post=False)
+    def learned(llr, q, bits, iters, ok):
+        ldpc_decode_f32(hbm, Z, llr, max_iter=T, w=w, early_term=True, bits=bits, iters=iters, ok=ok,
+                        want_post=False)
 
-    def learned8(llr, q):
-        return ldpc_decode_i8(hbm, Z, q, max_iter=T, wq_table=wq, early_term=True, want_post=False)
+    def learned8(llr, q, bits, iters, ok):
+        ldpc_decode_i8(hbm, Z, q, max_iter=T, wq_table=wq, early_term=True, bits=bits, iters=iters, ok=ok,
+                       want_post=False)
 
-    def fb32(llr, q, bits, iters, ok):
-        ldpc_fallback_f32(hbm, Z, llr, bits, iters, ok, max_iter=20, alpha=0.75)
+    def fb32(llr, q, bits, iters, ok, work):
+        ldpc_fallback_f32(hbm, Z, llr, bits, iters, ok, max_iter=20, alpha=0.75, work=work)
 
-    def fb8(llr, q, bits, iters, ok):
-        ldpc_fallback_i8(hbm, Z, q, bits, iters, ok, max_iter=20, wq=12)
+    def fb8(llr, q, bits, iters, ok, work):
+        ldpc_fallback_i8(hbm, Z, q, bits, iters, ok, max_iter=20, wq=12, work=work)
 
     return [_Dec("plain_nms_f32", plain, fb32), _Dec("learned_f32", learned, fb32),
             _Dec("learned_i8", learned8, fb8)]
 
 
-def sweep(hbm, Z, decs, ebn0_list, frames, chunk=1 << 17, seed=7, device="cuda", T=10):
+class SweepPipeline:
+    """One Monte-Carlo sweep chunk on fixed device buffers: seeded random
+    bits -> direct encoding -> BPSK/AWGN channel values -> int8 quantisation
+    (the frame stage), then per decoder form: decode (the decode stage),
+    first-pass counters, fallback re-decoding, final counters (the post
+    stage). The seeds (device int64 [2]: bits, noise) and the per-frame
+    noise deviation and LLR scale (device f32 [F]) are read by the kernels,
+    so the stages can be captured once in HIP graphs and replayed for every
+    chunk and Eb/N0 point after those buffers are refilled."""
+
+    def __init__(self, hbm, Z, decs, F, device="cuda"):
+        info = ldpc_code_info(hbm, Z)
+        self.hbm, self.Z, self.decs, self.F = hbm, Z, decs, F
+        self.N, self.K = info["N"], info["K"]
+        dev = device
+        self.seeds = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.sigma = torch.zeros(F, dtype=torch.float32, device=dev)
+        self.scale = torch.zeros(F, dtype=torch.float32, device=dev)
+        self.info = torch.empty((F, self.K), dtype=torch.uint8, device=dev)
+        self.cw = torch.empty((F, self.N), dtype=torch.uint8, device=dev)
+        self.llr = torch.empty((F, self.N), dtype=torch.float32, device=dev)
+        self.q = torch.empty((F, self.N), dtype=torch.int8, device=dev)
+        self.out = {d.name: dict(bits=torch.empty((F, self.N), dtype=torch.uint8, device=dev),
+                                 iters=torch.empty(F, dtype=torch.int32, device=dev),
+                                 ok=torch.empty(F, dtype=torch.uint8, device=dev),
+                                 work=torch.empty(F + 1, dtype=torch.int64, device=dev),
+                                 first=torch.zeros(4, dtype=torch.int64, device=dev),
+                                 final=torch.zeros(4, dtype=torch.int64, device=dev)) for d in decs}
+        self.graphs = None
+
+    def frame_stage(self):
+        ldpc_random_bits(self.seeds[0:1], self.F, self.K, out=self.info)
+        ldpc_encode(self.hbm, self.Z, self.info, cw=self.cw)
+        ldpc_awgn_llr(self.seeds[1:2], self.cw, self.sigma, self.scale, out=self.llr)
+        ldpc_quantize_i8(self.llr, out=self.q)
+
+    def decode_stage(self, d):
+        o = self.out[d.name]
+        d.run(self.llr, self.q, o["bits"], o["iters"], o["ok"])
+
+    def post_stage(self, d):
+        o = self.out[d.name]
+        ldpc_frame_stats(o["bits"], self.info, o["iters"], o["ok"], counters=o["first"])
+        d.fallback(self.llr, self.q, o["bits"], o["iters"], o["ok"], o["work"])
+        ldpc_frame_stats(o["bits"], self.info, o["iters"], o["ok"], counters=o["final"])
+
+    def set_point(self, ebn0_db, seed):
+        """Refills the seed and noise buffers (fill kernels, no host wait)."""
+        s2 = synth.sigma2_from_ebn0(float(ebn0_db), self.K / self.N)
+        self.sigma.fill_(math.sqrt(s2))
+        self.scale.fill_(2.0 / s2)
+        self.seeds[0].fill_(seed)
+        self.seeds[1].fill_(seed ^ 0x5DEECE66D)
+
+    def clear_counters(self):
+        for o in self.out.values():
+            o["first"].zero_()
+            o["final"].zero_()
+
+    def capture(self):
+        """Captures the frame stage and each decoder's decode and post stages
+        in HIP graphs (after one eager pass that loads every kernel)."""
+        self.frame_stage()
+        for d in self.decs:
+            self.decode_stage(d)
+            self.post_stage(d)
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        graphs = {}
+        with torch.cuda.stream(side):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                self.frame_stage()
+            graphs["frames"] = g
+            for d in self.decs:
+                gd, gp = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gd, stream=side):
+                    self.decode_stage(d)
+                with torch.cuda.graph(gp, stream=side):
+                    self.post_stage(d)
+                graphs[d.name] = (gd, gp)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graphs = graphs
+
+    def run_chunk(self, ms):
+        """One chunk at the current point; adds each decoder's decode time
+        (ms, events around the decode stage) to ms[name]."""
+        if self.graphs is not None:
+            self.graphs["frames"].replay()
+        else:
+            self.frame_stage()
+        for d in self.decs:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if self.graphs is not None:
+                self.graphs[d.name][0].replay()
+            else:
+                self.decode_stage(d)
+            e1.record()
+            if self.graphs is not None:
+                self.graphs[d.name][1].replay()
+            else:
+                self.post_stage(d)
+            ms.append((d.name, e0, e1))
+
+
+def chunk_seed(seed, point, chunk):
+    return seed * 7919 + point * 104729 + chunk
+
+
+def sweep(hbm, Z, decs, ebn0_list, frames, chunk=1 << 17, seed=7, device="cuda", T=10, graph=True):
     """FER/BER/iterations per decoder and Eb/N0 point, first pass and after
-    fallback, and decode throughput (info bits per second of decode time)."""
-    info = ldpc_code_info(hbm, Z)
-    K = info["K"]
+    fallback, and decode throughput (info bits per second of decode time).
+    Every chunk holds min(chunk, frames) frames (frames must be a multiple);
+    with graph=True each chunk replays the pipeline's captured HIP graphs,
+    otherwise it calls the same stages eagerly (identical results)."""
+    F = min(chunk, frames)
+    if frames % F:
+        raise ValueError(f"frames ({frames}) must be a multiple of the chunk ({F})")
+    pipe = SweepPipeline(hbm, Z, decs, F, device)
+    if graph:
+        pipe.set_point(ebn0_list[0], chunk_seed(seed, 0, 0))
+        pipe.capture()
+    K = pipe.K
     out = {d.name: [] for d in decs}
     for pi, eb in enumerate(ebn0_list):
-        first = {d.name: torch.zeros(4, dtype=torch.int64, device=device) for d in decs}
-        final = {d.name: torch.zeros(4, dtype=torch.int64, device=device) for d in decs}
+        pipe.clear_counters()
+        ev = []
+        for ci in range(frames // F):
+            pipe.set_point(eb, chunk_seed(seed, pi, ci))
+            pipe.run_chunk(ev)
+        torch.cuda.synchronize()
         ms = {d.name: 0.0 for d in decs}
-        done = 0
-        ci = 0
-        while done < frames:
-            F = min(chunk, frames - done)
-            bits_in, _, llr = make_frames(hbm, Z, F, eb, seed * 7919 + pi * 104729 + ci, device)
-            q = ldpc_quantize_i8(llr)
-            for d in decs:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                bits, _, iters, ok = d.run(llr, q)
-                e1.record()
-                ldpc_frame_stats(bits, bits_in, iters, ok, counters=first[d.name])
-                d.fallback(llr, q, bits, iters, ok)
-                ldpc_frame_stats(bits, bits_in, iters, ok, counters=final[d.name])
-                torch.cuda.synchronize()
-                ms[d.name] += e0.elapsed_time(e1)
-            done += F
-            ci += 1
+        for name, e0, e1 in ev:
+            ms[name] += e0.elapsed_time(e1)
         for d in decs:
-            a, b = first[d.name].cpu().numpy(), final[d.name].cpu().numpy()
+            a, b = (pipe.out[d.name][k].cpu().numpy() for k in ("first", "final"))
             out[d.name].append(dict(
                 ebn0=float(eb), frames=int(frames), fer=a[1] / frames, ber=a[0] / (frames * K),
                 mean_iters=a[2] / frames, failed_syndrome=int(a[3]),
                 # a frame that failed ran T first-pass iterations, then the fallback's
                 fer_fallback=b[1] / frames, mean_iters_total=(b[2] + T * a[3]) / frames,
-                gbit_s=frames * K / (ms[d.name] / 1e3) / 1e9))
+                gbit_s=frames * K / (ms[d.name] / 1e3) / 1e9,
+                counters_first=[int(x) for x in a], counters_final=[int(x) for x in b]))
     return out
 
 
