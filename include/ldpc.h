@@ -166,22 +166,25 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
 
 /*
  * Decode-layout autotuner. Times the code-specialised decode kernel of
- * `path` (0 FP32, 1 int8) over candidate layouts -- frame groups per
+ * `path` (0 FP32, 1 int8, 2 FP32 with a weight table w, 3 int8 with a
+ * weight table wq_table; a zero table is used for the timing, since the work
+ * does not depend on the weights) over candidate layouts -- frame groups per
  * workgroup, frames per thread, and how many block rows keep their gather
  * addresses in registers across iterations -- on F zero-valued frames at max_iter fixed
  * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
  * this code in this process (until ldpc_cache_clear). out[7] receives
  * {G, KF, FWp, threads, hoisted block rows, packed FP16, waves} of the
- * winner and *ms its time per launch. On the fixed-point path, for codes
+ * winner and *ms its time per launch. On path 1, for codes
  * whose values fit FP16 exactly (column weight <= 15), layouts that decode
  * two frames per lane in packed FP16 are candidates too (then G counts frame
  * pairs). A layout whose kernel needs more than 128 VGPRs per lane is also
  * timed compiled for one more wave per SIMD (waves = 3 above 168 VGPRs,
  * else 4); such a variant may spill at most 32 bytes of registers per lane
  * (scratch memory, extra HBM traffic) and is kept only if it is at least 5%
- * faster than the fastest layout that does not spill. Layouts the tuner
- * has not timed for the kernel at hand -- the default layout of an untuned
- * code, and any layout used with a weight table (w, wq_table) -- keep their
+ * faster than the fastest layout that does not spill. A decode with a
+ * weight table uses the layout tuned on path 2 or 3 when there is one. Layouts
+ * the tuner has not timed for the kernel at hand -- the default layout of an
+ * untuned code, and a plain path's layout used with a weight table -- keep their
  * frames but, where the kernel needs more than 168 VGPRs, hoist fewer block
  * rows' gather addresses (Mb/2, Mb/4 or 0: the deepest that fits three
  * waves per SIMD without spilling); the first such call on a code compiles
@@ -197,7 +200,7 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
  * autotuner may choose (the layouts change the launch shape and register
  * use, never the arithmetic of Sec. 4).
  * ldpc_decode_layouts: the layouts ldpc_autotune_decode times for this code
- *   and path, in its order, each as the 7 integers of its out[7]; writes at
+ *   and path (0..3 as for the tuner), in its order, each as the 7 integers of its out[7]; writes at
  *   most `cap` rows to out (int32 [cap][7], host) and returns the total count
  *   (>= 0) or a negative status. Compiles every candidate kernel (hipRTC) to
  *   read its registers and spills; no device memory is touched.
@@ -206,8 +209,8 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
  *   ldpc_decode_f32/_i8 calls on this code and path, as if the tuner had
  *   chosen it; NULL restores the default layout. LDPC_EINVAL if FWp or
  *   threads do not follow from G and KF, hoist is outside [0, Mb], waves is
- *   not 0, 3 or 4, or packed FP16 is asked for on the FP32 path, with KF 2
- *   or for a code of column weight above 15; LDPC_ERANGE if the layout does
+ *   not 0, 3 or 4, or packed FP16 is asked for on a path other than 1, with
+ *   KF 2 or for a code of column weight above 15; LDPC_ERANGE if the layout does
  *   not fit (threads, LDS).
  * Both need run-time specialisation (LDPC_ERANGE if LDPC_JIT=0).
  */

@@ -374,15 +374,20 @@ def ldpc_decode_q16(hbm, Z, llr, max_iter=10, wq=12, wrap=True, early_term=True,
     return bits, post, iters, ok
 
 
+# tuning paths: the two arithmetic paths, and each with a weight table
+_TUNE_PATHS = {"f32": 0, "i8": 1, "f32w": 2, "i8w": 3}
+
+
 def ldpc_autotune_decode(hbm, Z, path="f32", max_iter=10, F=16384, stream=None):
-    """Times candidate decode layouts for this code and keeps the fastest.
+    """Times candidate decode layouts for this code and keeps the fastest;
+    path "f32" / "i8", or "f32w" / "i8w" for the kernels with a weight table.
     Returns dict(G, KF, FWp, threads, hoist, h2, waves, ms); h2 = 1: two
     frames per lane in packed FP16 (fixed point), G frame pairs per
     workgroup; waves: occupancy target the kernel was compiled for (0: none)."""
     h = _hbm(hbm)
     out = np.zeros(7, np.int32)
     ms = np.zeros(1, np.float32)
-    p = {"f32": 0, "i8": 1}[path]
+    p = _TUNE_PATHS[path]
     _check(lib().ldpc_autotune_decode(_hptr(h), h.shape[0], h.shape[1], Z, p, int(max_iter), int(F),
                                       out.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p),
                                       _stream(stream)), "ldpc_autotune_decode")
@@ -397,7 +402,7 @@ def ldpc_decode_layouts(hbm, Z, path="f32"):
     """Every layout the decode autotuner times for this code and path, as
     dicts with the keys of ldpc_autotune_decode (compiles each candidate)."""
     h = _hbm(hbm)
-    p = {"f32": 0, "i8": 1}[path]
+    p = _TUNE_PATHS[path]
     n = lib().ldpc_decode_layouts(_hptr(h), h.shape[0], h.shape[1], Z, p, None, 0)
     if n < 0:
         _check(n, "ldpc_decode_layouts")
@@ -412,7 +417,7 @@ def ldpc_set_decode_layout(hbm, Z, path, layout):
     """Makes `layout` (a dict with the keys of ldpc_autotune_decode, or None
     for the default) the decode layout of this code and path."""
     h = _hbm(hbm)
-    p = {"f32": 0, "i8": 1}[path]
+    p = _TUNE_PATHS[path]
     arr = None
     if layout is not None:
         arr = np.array([int(layout[k]) for k in _LAYOUT_KEYS], np.int32)

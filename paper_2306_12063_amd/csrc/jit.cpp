@@ -386,6 +386,16 @@ DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, in
     return out;
 }
 
+DecodeLaunch decode_layout(const Sched &sc, int path, int mode)
+{
+    DecodeLaunch lc = jit_default_launch(sc, path);
+    const bool table = (path == 0 && mode == 1) || (path == 1 && mode == 2);
+    if (table && tuned_launch(sc, path + 2, &lc))
+        return lc;   // timed for the kernel with a weight table
+    tuned_launch(sc, path, &lc);
+    return usable_launch(sc, lc, path, mode);
+}
+
 DecodeLaunch jit_default_launch(const Sched &sc, int path)
 {
     const int per_row = sc.E / sc.Z;          // messages (and gather addresses) per thread

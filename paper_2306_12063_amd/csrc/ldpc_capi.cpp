@@ -289,9 +289,7 @@ int ldpc_decode_f32(const int16_t *hbm, int Mb, int Nb, int Z, const float *llr,
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     if (jit_enabled()) {
-        lc = jit_default_launch(sc, 0);
-        tuned_launch(sc, 0, &lc);
-        lc = usable_launch(sc, lc, 0, w ? 1 : 0);
+        lc = decode_layout(sc, 0, w ? 1 : 0);
         return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits,
                                  post, iters, ok, (hipStream_t)stream);
     }
@@ -323,9 +321,7 @@ int ldpc_decode_i8(const int16_t *hbm, int Mb, int Nb, int Z, const int8_t *llr,
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
     if (jit_enabled()) {
-        lc = jit_default_launch(sc, 1);
-        tuned_launch(sc, 1, &lc);
-        lc = usable_launch(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
+        lc = decode_layout(sc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
         return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset,
                                  wq, early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream);
     }
@@ -354,8 +350,7 @@ int ldpc_decode_f32_packed(const int16_t *hbm, int Mb, int Nb, int Z, const floa
     DecodeLaunch lc = jit_default_launch(sc, 0);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
-    tuned_launch(sc, 0, &lc);
-    lc = usable_launch(sc, lc, 0, w ? 1 : 0);
+    lc = decode_layout(sc, 0, w ? 1 : 0);
     return launch_jit_decode(sc, lc, 0, w ? 1 : 0, llr, nullptr, F, max_iter, alpha, 0, 0, early_term, w, bits, post,
                              iters, ok, (hipStream_t)stream, nullptr, true);
 }
@@ -384,8 +379,7 @@ int ldpc_decode_i8_packed(const int16_t *hbm, int Mb, int Nb, int Z, const int8_
     DecodeLaunch lc = jit_default_launch(sc, 1);
     if (lc.G < 1)
         return fail(LDPC_ERANGE, "code with N=%d does not fit the decoder's LDS budget", sc.N);
-    tuned_launch(sc, 1, &lc);
-    lc = usable_launch(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
+    lc = decode_layout(sc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0));
     return launch_jit_decode(sc, lc, 1, wq_table ? 2 : (wq > 0 ? 1 : 0), llr, nullptr, F, max_iter, 0.0f, offset, wq,
                              early_term, wq_table, bits, post, iters, ok, (hipStream_t)stream, nullptr, true);
 }
@@ -449,8 +443,8 @@ int ldpc_autotune_decode(const int16_t *hbm, int Mb, int Nb, int Z, int path, in
     int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
     if (rc)
         return rc;
-    if (path != 0 && path != 1)
-        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (path < 0 || path > 3)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32), 1 (int8), 2 (FP32 weight table) or 3 (int8 weight table)");
     if (max_iter < 1 || F < 1)
         return fail(LDPC_EINVAL, "max_iter and F must be >= 1");
     if (!out || !ms)
@@ -488,8 +482,8 @@ int ldpc_decode_layouts(const int16_t *hbm, int Mb, int Nb, int Z, int path, int
     int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
     if (rc)
         return rc;
-    if (path != 0 && path != 1)
-        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (path < 0 || path > 3)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32), 1 (int8), 2 (FP32 weight table) or 3 (int8 weight table)");
     if (cap < 0 || (cap > 0 && !out))
         return fail(LDPC_EINVAL, "negative capacity or null output pointer");
     if (!jit_enabled())
@@ -509,8 +503,8 @@ int ldpc_set_decode_layout(const int16_t *hbm, int Mb, int Nb, int Z, int path, 
     int rc = compile_sched(hbm, Mb, Nb, Z, true, &sc);
     if (rc)
         return rc;
-    if (path != 0 && path != 1)
-        return fail(LDPC_EINVAL, "path must be 0 (FP32) or 1 (int8)");
+    if (path < 0 || path > 3)
+        return fail(LDPC_EINVAL, "path must be 0 (FP32), 1 (int8), 2 (FP32 weight table) or 3 (int8 weight table)");
     if (!jit_enabled())
         return fail(LDPC_ERANGE, "decode layouts need run-time specialised kernels (LDPC_JIT=0 is set)");
     if (!layout) {
@@ -521,7 +515,8 @@ int ldpc_set_decode_layout(const int16_t *hbm, int Mb, int Nb, int Z, int path, 
     if (h2 != 0 && h2 != 1)
         return fail(LDPC_EINVAL, "packed-FP16 flag must be 0 or 1");
     if (h2 && (path != 1 || !h2_eligible(sc) || KF != 1))
-        return fail(LDPC_EINVAL, "two frames per lane needs the fixed-point path, KF = 1 and column weight <= 15");
+        return fail(LDPC_EINVAL, "two frames per lane needs the fixed-point path without a weight table, KF = 1 and "
+                    "column weight <= 15");
     DecodeLaunch lc = h2 ? make_h2_launch(sc, G, kMaxThreads) : make_launch(sc, 4, G, KF, kMaxThreads);
     if (lc.G < 1 || KF < 1 || KF > 2)
         return fail(LDPC_ERANGE, "layout G=%d KF=%d does not fit this code (threads, LDS or frames per workgroup)", G,

@@ -73,6 +73,10 @@ DecodeLaunch make_h2_launch(const Sched &sc, int G, int max_threads);
 // The layout to use for (path, mode): a packed-FP16 layout is replaced by
 // the default one where it does not apply (FP32, weight tables).
 DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode);
+// The layout of a decode call on arithmetic path `path` in kernel `mode`: a
+// layout the tuner timed for this kernel (with a weight table: tuning path
+// path + 2), else the plain path's tuned or default layout made usable.
+DecodeLaunch decode_layout(const Sched &sc, int path, int mode);
 
 // Kernel launchers (decode_kernels.hip). Return LDPC_OK or LDPC_EDEVICE.
 int launch_decode_f32(const Sched &sc, const DecodeLaunch &lc, const float *llr, const int64_t *fidx, int64_t F,
@@ -153,6 +157,12 @@ DecodeLaunch plan_decode(const Sched &sc, int elem_bytes, int kf_hint);
 DecodeLaunch make_launch(const Sched &sc, int elem_bytes, int G, int KF, int max_threads);
 
 // Decode layout chosen by the autotuner for this code and path, if any.
+// Tuning paths of the decode-layout autotuner: 0 FP32, 1 int8, 2 FP32 with a
+// weight table, 3 int8 with a weight table. The arithmetic path is path & 1;
+// the kernel mode is that of the plain decoder (alpha, offset) or of a
+// weight table.
+inline int tune_mode(int tpath) { return tpath == 2 ? 1 : (tpath == 3 ? 2 : 0); }
+inline bool mode_has_table(int tpath) { return tpath >= 2; }
 bool tuned_launch(const Sched &sc, int path, DecodeLaunch *out);
 void set_tuned_launch(const Sched &sc, int path, const DecodeLaunch &lc);
 void tune_cache_clear();

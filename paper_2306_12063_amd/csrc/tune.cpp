@@ -47,7 +47,8 @@ std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
     std::vector<DecodeLaunch> out;
     const int per_row = sc.E / sc.Z;
     const int hoists[5] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, sc.Mb / 4, 0};
-    // fixed point: two frames per lane in packed FP16 where the values fit
+    // fixed point without a weight table: two frames per lane in packed
+    // FP16 where the values fit
     if (path == 1 && h2_eligible(sc)) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
             DecodeLaunch lc = make_h2_launch(sc, G, kMaxThreads);
@@ -116,6 +117,8 @@ int tuner_layouts(const Sched &sc, int path, std::vector<DecodeLaunch> *out, std
     // hinted one may spill at most 32 bytes per lane.
     const char *lv = getenv("LDPC_TUNE_LOG");
     const bool log = lv && lv[0] == '1';
+    // tuning path: 0 FP32, 1 int8, 2 FP32 with a weight table, 3 int8 with a table
+    const int kpath = path & 1, mode = tune_mode(path);
     std::vector<DecodeLaunch> work = candidates(sc, 4, path);   // FP32 posteriors in LDS on both paths
     out->clear();
     if (scratch_out)
@@ -124,7 +127,7 @@ int tuner_layouts(const Sched &sc, int path, std::vector<DecodeLaunch> *out, std
         const DecodeLaunch lc = work[w];
         size_t scratch = 0;
         int vgprs = 0;
-        int rc = jit_decode_scratch(sc, lc, path, 0, &scratch, &vgprs);
+        int rc = jit_decode_scratch(sc, lc, kpath, mode, &scratch, &vgprs);
         if (rc)
             return rc;
         const size_t allowed = lc.waves ? 32 : 0;
@@ -149,8 +152,11 @@ int tuner_layouts(const Sched &sc, int path, std::vector<DecodeLaunch> *out, std
 int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStream_t stream, DecodeLaunch *best,
                     float *best_ms)
 {
-    const size_t in_bytes = (size_t)F * sc.N * (path == 0 ? 4 : 1);
-    void *llr = nullptr, *bits = nullptr, *iters = nullptr;
+    const int kpath = path & 1, mode = tune_mode(path);
+    const size_t in_bytes = (size_t)F * sc.N * (kpath == 0 ? 4 : 1);
+    // a zero weight table: the decode does the same work for any weights
+    const size_t w_bytes = mode_has_table(path) ? (size_t)max_iter * sc.Mb * sc.Nb * (kpath == 0 ? 4 : 1) : 0;
+    void *llr = nullptr, *bits = nullptr, *iters = nullptr, *wt = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = LDPC_OK;
     float best_t = 1e30f, spill_t = 1e30f;
@@ -162,11 +168,13 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
     if ((rc = tuner_layouts(sc, path, &work, &spills)))
         return rc;
     if (hipMalloc(&llr, in_bytes) != hipSuccess || hipMalloc(&bits, (size_t)F * sc.N) != hipSuccess ||
-        hipMalloc(&iters, (size_t)F * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc(&iters, (size_t)F * sizeof(int32_t)) != hipSuccess ||
+        (w_bytes && hipMalloc(&wt, w_bytes) != hipSuccess)) {
         rc = fail(LDPC_ENOMEM, "autotune: device allocation failed");
         goto done;
     }
-    if (hipMemsetAsync(llr, 0, in_bytes, stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+    if (hipMemsetAsync(llr, 0, in_bytes, stream) != hipSuccess ||
+        (w_bytes && hipMemsetAsync(wt, 0, w_bytes, stream) != hipSuccess) || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess) {
         rc = fail(LDPC_EDEVICE, "autotune: HIP setup failed");
         goto done;
@@ -177,14 +185,14 @@ int autotune_decode(const Sched &sc, int path, int max_iter, int64_t F, hipStrea
         const DecodeLaunch lc = work[w];
         const size_t scratch = spills[w];
         // the first launch warms the caches
-        rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr, (uint8_t *)bits,
+        rc = launch_jit_decode(sc, lc, kpath, mode, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, wt, (uint8_t *)bits,
                                nullptr, (int32_t *)iters, nullptr, stream);
         if (rc)
             goto done;
         const int reps = 3;
         hipEventRecord(e0, stream);
         for (int k = 0; k < reps && rc == LDPC_OK; ++k)
-            rc = launch_jit_decode(sc, lc, path, 0, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, nullptr,
+            rc = launch_jit_decode(sc, lc, kpath, mode, llr, nullptr, F, max_iter, 0.75f, 1, 0, 0, wt,
                                    (uint8_t *)bits, nullptr, (int32_t *)iters, nullptr, stream);
         hipEventRecord(e1, stream);
         if (rc)
@@ -232,6 +240,8 @@ done:
         (void)hipFree(bits);
     if (iters)
         (void)hipFree(iters);
+    if (wt)
+        (void)hipFree(wt);
     return rc;
 }
 

@@ -18,8 +18,8 @@ import numpy as np
 import torch
 
 import synth
-from . import (ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_encode, ldpc_fallback_f32, ldpc_fallback_i8,
-               ldpc_frame_stats, ldpc_quantize_i8, ldpc_random_bits, ldpc_awgn_llr)
+from . import (ldpc_autotune_decode, ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_encode, ldpc_fallback_f32,
+               ldpc_fallback_i8, ldpc_frame_stats, ldpc_quantize_i8, ldpc_random_bits, ldpc_awgn_llr)
 from .nms import nms_loss, quantize_weights
 
 
@@ -51,12 +51,15 @@ def make_frames(hbm, Z, F, ebn0_db, seed, device="cuda", sigma_scale=None):
 
 def iteration_weights(kind, T, device="cuda"):
     """Weights of the per-iteration losses in the training objective:
-    'uniform' (the mean over iterations), 'ramp' (proportional to t + 1) or
+    'uniform' (the mean over iterations), 'ramp' (proportional to t + 1),
+    'early' (proportional to T - t: early convergence weighs most) or
     'last' (the last iteration only); each sums to one."""
     if kind == "uniform":
         g = torch.ones(T)
     elif kind == "ramp":
         g = torch.arange(1, T + 1, dtype=torch.float32)
+    elif kind == "early":
+        g = torch.arange(T, 0, -1, dtype=torch.float32)
     elif kind == "last":
         g = torch.zeros(T)
         g[-1] = 1.0
@@ -113,10 +116,15 @@ class _Dec:
         self.name, self.run, self.fallback = name, run, fallback
 
 
-def decoders(hbm, Z, w, T=10):
+def decoders(hbm, Z, w, T=10, tune=False):
     """Plain NMS (alpha = 0.75), learned FP32 and learned int8 (1/16 steps);
-    each falls back to plain min-sum with 20 iterations for failed frames."""
+    each falls back to plain min-sum with 20 iterations for failed frames.
+    tune: first time each form's decode layouts for this code (the plain
+    FP32 kernel and the two kernels with a weight table)."""
     wq = quantize_weights(w)
+    if tune:
+        for path in ("f32", "f32w", "i8w"):
+            ldpc_autotune_decode(hbm, Z, path=path, max_iter=T)
 
     def plain(llr, q, bits, iters, ok):
         ldpc_decode_f32(hbm, Z, llr, max_iter=T, alpha=0.75, early_term=True, bits=bits, iters=iters, ok=ok,
@@ -309,8 +317,9 @@ def iters_at(points, ebn0):
 
 
 def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, seed=1, log_every=0,
-            train_range=(1.0, 4.0), lr=1e-2, lr_final=None, tie="none", iter_loss="uniform"):
-    """Trains a weight set for one code and compares the three decoder forms."""
+            train_range=(1.0, 4.0), lr=1e-2, lr_final=None, tie="none", iter_loss="uniform", tune=True):
+    """Trains a weight set for one code and compares the three decoder forms
+    (with tune, each on its own autotuned decode layout)."""
     if ebn0_list is None:
         ebn0_list = [1.0 + 0.25 * k for k in range(21)]
     t0 = time.perf_counter()
@@ -318,7 +327,7 @@ def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, s
                     lr_final=lr_final, tie=tie, iter_loss=iter_loss)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res = sweep(hbm, Z, decoders(hbm, Z, w), ebn0_list, eval_frames, seed=seed + 1)
+    res = sweep(hbm, Z, decoders(hbm, Z, w, tune=tune), ebn0_list, eval_frames, seed=seed + 1)
     summary = {}
     e_plain = ebn0_at_fer(res["plain_nms_f32"])
     for name, pts in res.items():
@@ -355,7 +364,7 @@ def main():
     ap.add_argument("--lr-final", type=float, default=None, help="cosine decay of the step size to this value")
     ap.add_argument("--tie", choices=["none", "layer"], default="none",
                     help="layer: one weight per (iteration, block row)")
-    ap.add_argument("--iter-loss", choices=["uniform", "ramp", "last"], default="uniform",
+    ap.add_argument("--iter-loss", choices=["uniform", "ramp", "early", "last"], default="uniform",
                     help="weights of the per-iteration losses in the objective")
     args = ap.parse_args()
     a, b, s = (float(x) for x in args.ebn0.split(":"))

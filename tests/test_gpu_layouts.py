@@ -60,6 +60,39 @@ def test_every_decode_layout_exact(code, path):
         P.ldpc_set_decode_layout(h, Z, path, None)
 
 
+@pytest.mark.parametrize("path", ["f32w", "i8w"])
+@pytest.mark.parametrize("code", [("wifi", "1/2", 81), ("wifi", "5/6", 81), ("wimax", "1/2", 96)],
+                         ids=lambda c: f"{c[0]}-{c[1]}-z{c[2]}")
+def test_every_weighted_layout_exact(code, path):
+    """The layouts the tuner times for the kernels with a weight table (FP32
+    weights; int8 weights in 1/16 steps), each installed as the tuned one:
+    bit-exact against the oracle with the same table."""
+    kind, rate, Z = code
+    h = synth.wifi_code(rate, Z) if kind == "wifi" else synth.wimax_code(rate, Z)
+    _, _, llr = oracle.llr_frames(h, Z, 67, 1.5, 29)
+    q = oracle.quantize_i8(llr)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.5, 1.0, (10,) + h.shape).astype(np.float32)
+    wq = oracle.quantize_weights(w)
+    layouts = P.ldpc_decode_layouts(h, Z, path)
+    assert layouts and not any(l["h2"] for l in layouts)
+    want = {et: (oracle.decode_f32(h, Z, llr, max_iter=10, early_term=et, w=w) if path == "f32w" else
+                 oracle.decode_i8(h, Z, q, max_iter=10, wq_table=wq, early_term=et)) for et in (True, False)}
+    try:
+        for lay in layouts:
+            P.ldpc_set_decode_layout(h, Z, path, lay)
+            for et in (True, False):
+                if path == "f32w":
+                    got = P.ldpc_decode_f32(h, Z, _gpu(llr), max_iter=10, w=_gpu(w), early_term=et)
+                else:
+                    got = P.ldpc_decode_i8(h, Z, _gpu(q), max_iter=10, wq_table=_gpu(wq), early_term=et)
+                torch.cuda.synchronize()
+                for g, ww, what in zip(got, want[et], ("bits", "posteriors", "iterations", "ok")):
+                    assert np.array_equal(g.cpu().numpy(), ww), (lay, et, what)
+    finally:
+        P.ldpc_set_decode_layout(h, Z, path, None)
+
+
 def test_set_layout_validation():
     h = synth.wifi_code("1/2", 81)
     lay = P.ldpc_decode_layouts(h, 81, "f32")[0]
@@ -69,6 +102,9 @@ def test_set_layout_validation():
             P.ldpc_set_decode_layout(h, 81, "f32", bad)
     with pytest.raises(P.LdpcError):
         P.ldpc_set_decode_layout(h, 81, "i8", {**lay, "G": 40})
+    h2lay = next(l for l in P.ldpc_decode_layouts(h, 81, "i8") if l["h2"])
+    with pytest.raises(P.LdpcError):   # no packed layout with a weight table
+        P.ldpc_set_decode_layout(h, 81, "i8w", h2lay)
     P.ldpc_set_decode_layout(h, 81, "f32", None)
 
 
