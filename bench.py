@@ -480,8 +480,8 @@ def learned_gain(train_frames, eval_frames, parity=True):
     code's waterfall, batch 4096, Adam from 1e-2 with a cosine decay to
     1e-3, per-iteration BCE weighted toward early iterations (T - t).
     Evaluation: every decoder on the same frames (graph-replayed sweep
-    chunks), early termination on, 10 iterations, each form on its own
-    autotuned decode layout."""
+    chunks), early termination on, 10 iterations, each form on the decode
+    layout that runs its sweep workload fastest (timed at the middle point)."""
     import synth
     from paper_2306_12063_amd import learned
     rnd = lambda v, n=3: None if v is None else round(float(v), n)
@@ -510,7 +510,8 @@ def learned_gain(train_frames, eval_frames, parity=True):
             "iter_reduction": {k: rnd(v.get("iter_reduction")) for k, v in sm.items() if k != "plain_nms_f32"},
             "decode_gbit_s": {k: rnd(v["gbit_s"], 2) for k, v in sm.items()},
             "decode_vs_plain": {k: rnd(v["gbit_s"] / sm["plain_nms_f32"]["gbit_s"]) for k, v in sm.items()
-                                if k != "plain_nms_f32"}}
+                                if k != "plain_nms_f32"},
+            "decode_layouts": r["layouts"]}
         if par is not None:
             out[name]["parity"] = par
     return out

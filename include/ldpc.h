@@ -174,7 +174,7 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
  * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
  * this code in this process (until ldpc_cache_clear). out[7] receives
  * {G, KF, FWp, threads, hoisted block rows, packed FP16, waves} of the
- * winner and *ms its time per launch. On path 1, for codes
+ * winner and *ms its time per launch. On paths 1 and 3, for codes
  * whose values fit FP16 exactly (column weight <= 15), layouts that decode
  * two frames per lane in packed FP16 are candidates too (then G counts frame
  * pairs). A layout whose kernel needs more than 128 VGPRs per lane is also

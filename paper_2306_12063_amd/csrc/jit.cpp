@@ -376,7 +376,7 @@ static DecodeLaunch three_wave_layout(const Sched &sc, const DecodeLaunch &lc, i
 DecodeLaunch usable_launch(const Sched &sc, const DecodeLaunch &lc, int path, int mode)
 {
     DecodeLaunch out = lc;
-    if (lc.h2 && (path != 1 || mode == 2 || !h2_eligible(sc)))
+    if (lc.h2 && (path != 1 || !h2_eligible(sc)))
         out = single_frame_launch(sc);
     // a layout the tuner did not time for this kernel: the default layout,
     // or a weighted mode (its kernel needs more registers than the plain one)
@@ -490,8 +490,8 @@ int launch_jit_decode(const Sched &sc, const DecodeLaunch &lc, int path, int mod
                       const void *wt, uint8_t *bits, void *post, int32_t *iters, uint8_t *ok, hipStream_t stream,
                       const int64_t *Fdev, bool packed)
 {
-    if (lc.h2 && (path != 1 || mode == 2))
-        return fail(LDPC_EINVAL, "internal: a two-frames-per-lane layout was chosen for path %d mode %d", path, mode);
+    if (lc.h2 && path != 1)
+        return fail(LDPC_EINVAL, "internal: a two-frames-per-lane layout was chosen for path %d", path);
     hipFunction_t fn;
     int rc = get_decode_function(sc, lc, path, mode, &fn, packed);
     if (rc)

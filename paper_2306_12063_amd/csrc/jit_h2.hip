@@ -160,6 +160,24 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
         R[e] = 0u;
     const u32 beta = W((h2){(_Float16)(float)offset, (_Float16)(float)offset});
     const float wqf = (float)wq;
+#if LDPC_MODE == 2
+    // weight table: the weights of iterations t (buffer t & 1) and t + 1 in
+    // LDS, copied one iteration ahead; row i's weights at i*WROW + e as a
+    // 16-bit pair (the same weight for both frames), 16-byte aligned rows
+    // read as broadcast loads of four
+    constexpr int WROW = (MAXD + 3) / 4 * 4;
+    __shared__ __attribute__((aligned(16))) u32 Wst[2][MB * WROW];
+    auto stage_weights = [&](int t) {
+        for (int k = tid; k < MB * WROW; k += LDPC_THREADS) {
+            const int i = k / WROW, e = k - i * WROW;
+            if (e < kDeg[i]) {
+                const u32 w = wt[(i64)t * (MB * NB) + i * NB + kCol[i][e]];
+                Wst[t & 1][k] = w | (w << 16);
+            }
+        }
+    };
+    stage_weights(0);
+#endif
     __syncthreads();
 
     // outputs of frame slot `slot` (bits, posteriors) from LDS, by the whole workgroup
@@ -200,6 +218,13 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
             constexpr int i = decltype(ic)::value;
             constexpr int d = kDeg[i];
             constexpr int eo = edge_off(i);
+#if LDPC_MODE == 2
+            // the next iteration's weights, after this layer's barrier (the
+            // buffer was last read in iteration t - 1)
+            if constexpr (i == 0)
+                if (t + 1 < max_iter)
+                    stage_weights(t + 1);
+#endif
             int rr = r;
             if constexpr (i >= LDPC_HOIST)
                 asm volatile("" : "+v"(rr));
@@ -235,6 +260,33 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                 const u32 par = xor_bits<d>(Q) & 0x80008000u;
                 const h2 cap = {(_Float16)127.0f, (_Float16)127.0f};
                 const h2 c1 = __builtin_elementwise_minimum(m1, cap), c2 = __builtin_elementwise_minimum(m2, cap);
+#if LDPC_MODE == 2
+                // a weight per edge: magnitude min(127, (wq * m + 8) >> 4) on
+                // 16-bit integer lanes, m = min2 at the row's minimum and min1
+                // elsewhere; the clipped minima as integers (c + 1024 has the
+                // integer c in its low ten bits)
+                const h2 k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
+                const u32 C1 = W(c1 + k1024) & 0x03ff03ffu, C2 = W(c2 + k1024) & 0x03ff03ffu;
+                const u2 dC = V(C1) - V(C2), eight = {8, 8}, c127 = {127, 127};
+                u32 one_w = 0x00010001u;
+                asm volatile("" : "+v"(one_w));   // keeps min(d, 1) * dC as one multiply-add, not two selects
+                const u2 one_u = V(one_w);
+                // -1024, or +1024 in a half whose parity is odd: adding it to
+                // the (signed) 1024 + magnitude leaves the signed magnitude
+                const u32 ybias = 0xe400e400u ^ par;
+                const uint4 *wrow = (const uint4 *)&Wst[t & 1][i * WROW];
+                u32 bad = 0, hw = 0;
+#pragma unroll
+                for (int e = 0; e < d; ++e) {
+                    const uint4 w4 = wrow[e / 4];
+                    const u32 we = (e % 4 == 0) ? w4.x : (e % 4 == 1) ? w4.y : (e % 4 == 2) ? w4.z : w4.w;
+                    const u2 c = __builtin_elementwise_min(V(W(A[e])) - V(W(m1)), one_u);   // 0 at the minimum
+                    const u2 ms = c * dC + V(C2);
+                    const u2 mg = __builtin_elementwise_min((V(we) * ms + eight) >> 4, c127);
+                    const u32 mag = W(H(W(mg) | 0x64006400u | par) + H(ybias));
+                    const u32 rv = (Q[e] & 0x80008000u) ^ mag;
+                    R[eo + e] = rv;
+#else
                 h2 n1, n2;
 #if LDPC_MODE == 0
                 {
@@ -257,6 +309,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                     const h2 u = __builtin_elementwise_min(__builtin_elementwise_max(m1p1 - A[e], zero_h), one_h);
                     const u32 rv = (Q[e] & 0x80008000u) ^ W(__builtin_elementwise_fma(u, dl, n1s));
                     R[eo + e] = rv;
+#endif
                     const u32 lv = W(H(Q[e]) + H(rv));
                     stb(Ls, ix[e], lv);
                     if (i == MB - 1) {   // row parities of the hard decisions, two edges at a time

@@ -514,9 +514,9 @@ int ldpc_set_decode_layout(const int16_t *hbm, int Mb, int Nb, int Z, int path, 
     const int G = layout[0], KF = layout[1], hoist = layout[4], h2 = layout[5], waves = layout[6];
     if (h2 != 0 && h2 != 1)
         return fail(LDPC_EINVAL, "packed-FP16 flag must be 0 or 1");
-    if (h2 && (path != 1 || !h2_eligible(sc) || KF != 1))
-        return fail(LDPC_EINVAL, "two frames per lane needs the fixed-point path without a weight table, KF = 1 and "
-                    "column weight <= 15");
+    if (h2 && ((path & 1) != 1 || !h2_eligible(sc) || KF != 1))
+        return fail(LDPC_EINVAL, "two frames per lane needs the fixed-point path (1 or 3), KF = 1 and column "
+                    "weight <= 15");
     DecodeLaunch lc = h2 ? make_h2_launch(sc, G, kMaxThreads) : make_launch(sc, 4, G, KF, kMaxThreads);
     if (lc.G < 1 || KF < 1 || KF > 2)
         return fail(LDPC_ERANGE, "layout G=%d KF=%d does not fit this code (threads, LDS or frames per workgroup)", G,

@@ -47,9 +47,9 @@ std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
     std::vector<DecodeLaunch> out;
     const int per_row = sc.E / sc.Z;
     const int hoists[5] = {sc.Mb, (3 * sc.Mb + 3) / 4, sc.Mb / 2, sc.Mb / 4, 0};
-    // fixed point without a weight table: two frames per lane in packed
-    // FP16 where the values fit
-    if (path == 1 && h2_eligible(sc)) {
+    // fixed point (with or without a weight table): two frames per lane in
+    // packed FP16 where the values fit
+    if ((path & 1) == 1 && h2_eligible(sc)) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
             DecodeLaunch lc = make_h2_launch(sc, G, kMaxThreads);
             if (lc.G < 1 || (double)(G * sc.Z) / lc.threads < 0.85)

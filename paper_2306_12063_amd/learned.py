@@ -18,8 +18,9 @@ import numpy as np
 import torch
 
 import synth
-from . import (ldpc_autotune_decode, ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_encode, ldpc_fallback_f32,
-               ldpc_fallback_i8, ldpc_frame_stats, ldpc_quantize_i8, ldpc_random_bits, ldpc_awgn_llr)
+from . import (ldpc_code_info, ldpc_decode_f32, ldpc_decode_i8, ldpc_decode_layouts, ldpc_encode, ldpc_fallback_f32,
+               ldpc_fallback_i8, ldpc_frame_stats, ldpc_quantize_i8, ldpc_random_bits, ldpc_set_decode_layout,
+               ldpc_awgn_llr)
 from .nms import nms_loss, quantize_weights
 
 
@@ -110,21 +111,17 @@ def train(hbm, Z, T=10, frames=1 << 20, batch=4096, lr=1e-2, ebn0_range=(1.0, 4.
 
 class _Dec:
     """One decoder form of the comparison: run(llr, q, bits, iters, ok)
-    decodes into the given buffers, fallback(...) re-decodes failed frames."""
+    decodes into the given buffers, fallback(...) re-decodes failed frames;
+    path names its kernel's decode layouts ("f32", "f32w", "i8w")."""
 
-    def __init__(self, name, run, fallback):
-        self.name, self.run, self.fallback = name, run, fallback
+    def __init__(self, name, run, fallback, path):
+        self.name, self.run, self.fallback, self.path = name, run, fallback, path
 
 
-def decoders(hbm, Z, w, T=10, tune=False):
+def decoders(hbm, Z, w, T=10):
     """Plain NMS (alpha = 0.75), learned FP32 and learned int8 (1/16 steps);
-    each falls back to plain min-sum with 20 iterations for failed frames.
-    tune: first time each form's decode layouts for this code (the plain
-    FP32 kernel and the two kernels with a weight table)."""
+    each falls back to plain min-sum with 20 iterations for failed frames."""
     wq = quantize_weights(w)
-    if tune:
-        for path in ("f32", "f32w", "i8w"):
-            ldpc_autotune_decode(hbm, Z, path=path, max_iter=T)
 
     def plain(llr, q, bits, iters, ok):
         ldpc_decode_f32(hbm, Z, llr, max_iter=T, alpha=0.75, early_term=True, bits=bits, iters=iters, ok=ok,
@@ -144,8 +141,39 @@ def decoders(hbm, Z, w, T=10, tune=False):
     def fb8(llr, q, bits, iters, ok, work):
         ldpc_fallback_i8(hbm, Z, q, bits, iters, ok, max_iter=20, wq=12, work=work)
 
-    return [_Dec("plain_nms_f32", plain, fb32), _Dec("learned_f32", learned, fb32),
-            _Dec("learned_i8", learned8, fb8)]
+    return [_Dec("plain_nms_f32", plain, fb32, "f32"), _Dec("learned_f32", learned, fb32, "f32w"),
+            _Dec("learned_i8", learned8, fb8, "i8w")]
+
+
+def tune_on_frames(hbm, Z, decs, ebn0, F=1 << 17, seed=12345, reps=2):
+    """Keeps, for each decoder form, the decode layout (among those the
+    library's tuner would time) that decodes F frames at `ebn0` fastest with
+    early termination, i.e. on the sweep's own workload rather than at fixed
+    iterations; returns {form: layout}."""
+    _, _, llr = make_frames(hbm, Z, F, ebn0, seed)
+    q = ldpc_quantize_i8(llr)
+    N, K = llr.shape[1], ldpc_code_info(hbm, Z)["K"]
+    bits = torch.empty((F, N), dtype=torch.uint8, device=llr.device)
+    iters = torch.empty(F, dtype=torch.int32, device=llr.device)
+    ok = torch.empty(F, dtype=torch.uint8, device=llr.device)
+    chosen = {}
+    for d in decs:
+        best = None
+        for lay in ldpc_decode_layouts(hbm, Z, d.path):
+            ldpc_set_decode_layout(hbm, Z, d.path, lay)
+            d.run(llr, q, bits, iters, ok)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                d.run(llr, q, bits, iters, ok)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if best is None or ms < best[0]:
+                best = (ms, lay)
+        ldpc_set_decode_layout(hbm, Z, d.path, best[1])
+        chosen[d.name] = dict(best[1], ms=round(best[0], 4))
+    return chosen
 
 
 class SweepPipeline:
@@ -319,7 +347,7 @@ def iters_at(points, ebn0):
 def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, seed=1, log_every=0,
             train_range=(1.0, 4.0), lr=1e-2, lr_final=None, tie="none", iter_loss="uniform", tune=True):
     """Trains a weight set for one code and compares the three decoder forms
-    (with tune, each on its own autotuned decode layout)."""
+    (with tune, each on the decode layout fastest on the sweep's workload)."""
     if ebn0_list is None:
         ebn0_list = [1.0 + 0.25 * k for k in range(21)]
     t0 = time.perf_counter()
@@ -327,7 +355,9 @@ def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, s
                     lr_final=lr_final, tie=tie, iter_loss=iter_loss)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res = sweep(hbm, Z, decoders(hbm, Z, w, tune=tune), ebn0_list, eval_frames, seed=seed + 1)
+    decs = decoders(hbm, Z, w)
+    layouts = tune_on_frames(hbm, Z, decs, ebn0_list[len(ebn0_list) // 2]) if tune else None
+    res = sweep(hbm, Z, decs, ebn0_list, eval_frames, seed=seed + 1)
     summary = {}
     e_plain = ebn0_at_fer(res["plain_nms_f32"])
     for name, pts in res.items():
@@ -342,7 +372,7 @@ def compare(hbm, Z, train_frames=1 << 20, eval_frames=1 << 18, ebn0_list=None, s
             summary[name]["iter_reduction"] = (None if it is None or base == 0 else 1.0 - it / base)
     return dict(train_seconds=t_train, loss_first=hist[0], loss_last=float(np.mean(hist[-16:])),
                 train_range=list(train_range), lr=lr, lr_final=lr_final, tie=tie, iter_loss=iter_loss,
-                summary=summary, sweep=res,
+                summary=summary, sweep=res, layouts=layouts,
                 weights=w.cpu().numpy().round(5).tolist(), w=w)
 
 

@@ -65,8 +65,9 @@ def test_every_decode_layout_exact(code, path):
                          ids=lambda c: f"{c[0]}-{c[1]}-z{c[2]}")
 def test_every_weighted_layout_exact(code, path):
     """The layouts the tuner times for the kernels with a weight table (FP32
-    weights; int8 weights in 1/16 steps), each installed as the tuned one:
-    bit-exact against the oracle with the same table."""
+    weights; int8 weights in 1/16 steps, one or two frames per lane), each
+    installed as the tuned one: bit-exact against the oracle with the same
+    table."""
     kind, rate, Z = code
     h = synth.wifi_code(rate, Z) if kind == "wifi" else synth.wimax_code(rate, Z)
     _, _, llr = oracle.llr_frames(h, Z, 67, 1.5, 29)
@@ -75,7 +76,9 @@ def test_every_weighted_layout_exact(code, path):
     w = rng.uniform(0.5, 1.0, (10,) + h.shape).astype(np.float32)
     wq = oracle.quantize_weights(w)
     layouts = P.ldpc_decode_layouts(h, Z, path)
-    assert layouts and not any(l["h2"] for l in layouts)
+    assert layouts
+    # the int8 table runs two frames per lane in packed FP16 too; FP32 never does
+    assert any(l["h2"] for l in layouts) == (path == "i8w")
     want = {et: (oracle.decode_f32(h, Z, llr, max_iter=10, early_term=et, w=w) if path == "f32w" else
                  oracle.decode_i8(h, Z, q, max_iter=10, wq_table=wq, early_term=et)) for et in (True, False)}
     try:
@@ -103,8 +106,10 @@ def test_set_layout_validation():
     with pytest.raises(P.LdpcError):
         P.ldpc_set_decode_layout(h, 81, "i8", {**lay, "G": 40})
     h2lay = next(l for l in P.ldpc_decode_layouts(h, 81, "i8") if l["h2"])
-    with pytest.raises(P.LdpcError):   # no packed layout with a weight table
-        P.ldpc_set_decode_layout(h, 81, "i8w", h2lay)
+    with pytest.raises(P.LdpcError):   # no packed FP16 on the FP32 table path
+        P.ldpc_set_decode_layout(h, 81, "f32w", h2lay)
+    P.ldpc_set_decode_layout(h, 81, "i8w", h2lay)
+    P.ldpc_set_decode_layout(h, 81, "i8w", None)
     P.ldpc_set_decode_layout(h, 81, "f32", None)
 
 
