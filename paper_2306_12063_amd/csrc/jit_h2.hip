@@ -134,9 +134,12 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
     __shared__ u32 Ls[PAD + N * FWP];
     __shared__ int unsat[FW];
     const int tid = threadIdx.x;
-    const int g = tid / Z;
-    const int r = tid - g * Z;
-    const bool lane_on = g < G;
+    // lanes interleave the workgroup's frame groups: a wave holds about
+    // 64 / G consecutive rows of each, so no two of its lanes read rows of
+    // one block column 64 apart (the same LDS bank)
+    const int g = tid % G;
+    const int r = tid / G;
+    const bool lane_on = tid < G * Z;
     const i64 f0 = (i64)blockIdx.x * FW;
     _Float16 *Lh = (_Float16 *)Ls;
     for (int slot = 0; slot < FW; ++slot) {
