@@ -108,8 +108,8 @@ def test_batch_graph_replay(wimax_set):
 
 
 def test_batch_full_size_sampled(wimax_set):
-    # 2^18 frames with uniformly drawn code ids in one persistent launch;
-    # the oracle checks a sample of frames.
+    # 2^18 frames with uniformly drawn code ids in one persistent launch,
+    # FP32 and int8; the oracle checks a sample of frames.
     codes, cs = wimax_set
     F = 1 << 18
     rng = np.random.default_rng(3)
@@ -142,6 +142,18 @@ def test_batch_full_size_sampled(wimax_set):
         wb, wp, wi, _ = oracle.decode_f32(h, Z, lh[off[f]:off[f] + N][None], max_iter=10, early_term=False)
         assert np.array_equal(bh[off[f]:off[f] + N], wb[0]) and np.array_equal(ph[off[f]:off[f] + N], wp[0])
         assert ih[f] == wi[0]
+    # the int8 path (two frames per lane in packed FP16) on the same frames
+    q = P.ldpc_quantize_i8(llr)
+    bits, post, iters, ok = cs.decode_i8(torch.from_numpy(cid).to(DEV), d_off, q, max_iter=10, offset=1,
+                                         early_term=False)
+    torch.cuda.synchronize()
+    qh, bh, ph, ih, oh = (t.cpu().numpy() for t in (q, bits, post, iters, ok))
+    for f in np.concatenate([[0, F - 1], rng.choice(F, 38, replace=False)]):
+        _, Z, h = codes[cid[f]]
+        N = 24 * Z
+        wb, wp, wi, wo = oracle.decode_i8(h, Z, qh[off[f]:off[f] + N][None], max_iter=10, offset=1, early_term=False)
+        assert np.array_equal(bh[off[f]:off[f] + N], wb[0]) and np.array_equal(ph[off[f]:off[f] + N], wp[0])
+        assert ih[f] == wi[0] and oh[f] == wo[0]
 
 
 def test_batch_autotune_keeps_parity():
