@@ -454,18 +454,20 @@ def _small_code_host(h, Zs, llr, K):
 
 def small_code(P, torch, dev):
     """Untimed record: the small Wi-Fi-shaped rate-1/2 code at Z=27 (N=648),
-    1000 frames at 2 dB, FP32 NMS with early termination (launch-bound)."""
+    1000 frames at 2 dB, FP32 NMS with early termination (latency-bound: few
+    workgroups), on the layout the tuner picks for 1000 frames."""
     import synth
     Zs, F = 27, 1000
     h = synth.wifi_code("1/2", Zs)
     K = P.ldpc_code_info(h, Zs)["K"]
     bits_in, llr, _ = _frames_at(P, h, Zs, F, EBN0_DB, SEED + 7, dev)
+    lay = P.ldpc_autotune_decode(h, Zs, path="f32", max_iter=ITERS, F=F)   # tuned for this small batch
     run = lambda: P.ldpc_decode_f32(h, Zs, llr, max_iter=ITERS, alpha=ALPHA, early_term=True, want_post=False)
     ms, fer, it = _decode_stats(P, torch, run, bits_in, 20)
     return _small_code_host(h, Zs, llr, K), {"workload": f"Wi-Fi-shaped synthetic rate-1/2 code, Z={Zs} (N=648), {F} frames at {EBN0_DB} dB, FP32 "
                         f"NMS alpha={ALPHA}, at most {ITERS} iterations with early termination",
             "ms": round(ms, 4), "gbit_s": round(F * K / (ms / 1e3) / 1e9, 3), "fer": round(float(fer), 5),
-            "mean_iters": round(float(it), 3)}
+            "mean_iters": round(float(it), 3), "layout": {k: lay[k] for k in ("G", "KF", "threads", "hoist", "waves")}}
 
 
 def learned_gain(train_frames, eval_frames, parity=True):

@@ -169,8 +169,10 @@ int ldpc_shift_packed(const uint8_t *in, uint8_t *out, int64_t F, int Z, int s, 
  * `path` (0 FP32, 1 int8, 2 FP32 with a weight table w, 3 int8 with a
  * weight table wq_table; a zero table is used for the timing, since the work
  * does not depend on the weights) over candidate layouts -- frame groups per
- * workgroup, frames per thread, and how many block rows keep their gather
- * addresses in registers across iterations -- on F zero-valued frames at max_iter fixed
+ * workgroup (those whose lanes are at least 85% busy, and for Z <= 64 the
+ * single-wave ones, which suit small batches), frames per thread, and how
+ * many block rows keep their gather addresses in registers across
+ * iterations -- on F zero-valued frames at max_iter fixed
  * iterations, and keeps the fastest for later ldpc_decode_f32/_i8 calls on
  * this code in this process (until ldpc_cache_clear). out[7] receives
  * {G, KF, FWp, threads, hoisted block rows, packed FP16, waves} of the

@@ -34,8 +34,13 @@ std::string tune_key(const Sched &sc, int path)
     return k;
 }
 
+// A workgroup of one wave (codes with Z <= 64): no barrier waits on other
+// waves, and a small batch spreads over more workgroups, so such layouts are
+// candidates however many of their lanes idle.
+bool single_wave(const Sched &sc, int G) { return G * sc.Z <= 64; }
+
 // Candidate layouts: workgroups of at most 256 threads whose lanes are at
-// least 85% busy, one or two frames per thread, and the number of block rows
+// least 85% busy (or of a single wave), one or two frames per thread, and the number of block rows
 // whose gather addresses stay in registers (all, three quarters, half, a
 // quarter, none).
 // A thread keeps KF messages per edge of its rows in VGPRs, plus an address
@@ -52,7 +57,7 @@ std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
     if ((path & 1) == 1 && h2_eligible(sc)) {
         for (int G = 1; G * sc.Z <= kMaxThreads; ++G) {
             DecodeLaunch lc = make_h2_launch(sc, G, kMaxThreads);
-            if (lc.G < 1 || (double)(G * sc.Z) / lc.threads < 0.85)
+            if (lc.G < 1 || (!single_wave(sc, G) && (double)(G * sc.Z) / lc.threads < 0.85))
                 continue;
             int last = -1;
             for (int h : hoists) {
@@ -69,7 +74,7 @@ std::vector<DecodeLaunch> candidates(const Sched &sc, int elem_bytes, int path)
             DecodeLaunch lc = make_launch(sc, elem_bytes, G, KF, kMaxThreads);
             if (lc.G < 1)
                 continue;
-            if ((double)(G * sc.Z) / lc.threads < 0.85)
+            if (!single_wave(sc, G) && (double)(G * sc.Z) / lc.threads < 0.85)
                 continue;
             int last = -1;
             for (int h : hoists) {

@@ -25,7 +25,7 @@ def _gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-CODES = [("wifi", r, 81) for r in synth.WIFI_RATES] + [("wimax", "1/2", 96)]
+CODES = [("wifi", r, 81) for r in synth.WIFI_RATES] + [("wimax", "1/2", 96), ("wifi", "1/2", 27)]
 
 
 @pytest.mark.parametrize("path", ["f32", "i8"])
