@@ -142,17 +142,46 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
     const bool lane_on = tid < G * Z;
     const i64 f0 = (i64)blockIdx.x * FW;
     _Float16 *Lh = (_Float16 *)Ls;
-    for (int slot = 0; slot < FW; ++slot) {
-        const i64 fg = f0 + slot;
-        const bool real = fg < F;
-        const signed char *p = real ? llr + (fidx ? fidx[fg] : fg) * (i64)N : nullptr;
-        for (int n = tid; n < N; n += LDPC_THREADS)
-            Lh[2 * (PAD + n * FWP + (slot >> 1)) + (slot & 1)] = real ? (_Float16)(float)p[n] : (_Float16)0.0f;
-    }
+    // Channel values into LDS (frame slot s in half s & 1 of pair s >> 1; a
+    // slot past F holds zeros). The FW frames are one flat range of FW*N
+    // values; each thread puts up to 16 loads in flight before it waits for
+    // the first, so a workgroup pays one or two round trips to HBM before its
+    // first layer, not one per frame and pass.
+    __shared__ i64 frow[FW];   // row of each frame slot's buffers, -1 past F
     __shared__ int conv[FW];
     if (tid < FW) {
+        const i64 fg = f0 + tid;
+        frow[tid] = fg < F ? (fidx ? fidx[fg] : fg) : (i64)-1;
         unsat[tid] = 0;
         conv[tid] = 0;
+    }
+    __syncthreads();
+    {
+        constexpr int TOT = FW * N;
+        constexpr int PER = (TOT + LDPC_THREADS - 1) / LDPC_THREADS;
+        constexpr int CH = PER < 16 ? PER : 16;
+        for (int j0 = 0; j0 < PER; j0 += CH) {
+            signed char v[CH];
+            int dst[CH];
+            // loads are unconditional (a value past the range or of a slot
+            // past F is read from frame slot 0, which exists) so that none
+            // waits for another; the store below zeroes the latter
+            bool real[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int k = (j0 + j) * LDPC_THREADS + tid;
+                const int kk = k < TOT ? k : 0;
+                const int slot = kk / N, n = kk - slot * N;
+                const i64 row = frow[slot];
+                v[j] = llr[(row >= 0 ? row : frow[0]) * (i64)N + n];
+                real[j] = row >= 0;
+                dst[j] = k < TOT ? 2 * (PAD + n * FWP + (slot >> 1)) + (slot & 1) : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (dst[j] >= 0)
+                    Lh[dst[j]] = real[j] ? (_Float16)(float)v[j] : (_Float16)0.0f;
+        }
     }
     const bool act0 = lane_on && f0 + 2 * g < F, act1 = lane_on && f0 + 2 * g + 1 < F;
     bool act[2] = {act0, act1};
@@ -183,12 +212,13 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
 #endif
     __syncthreads();
 
-    // outputs of frame slot `slot` (bits, posteriors) from LDS, by the whole workgroup
-    auto write_frame = [&](int slot) {
-        const i64 fg = f0 + slot;
-        if (fg >= F)
+    // outputs of frame slot `slot` (bits, posteriors) from LDS, by the whole
+    // workgroup; wide: four bits per 32-bit store (after the iterations only:
+    // inside them its registers would spill)
+    auto write_frame = [&](int slot, bool wide) {
+        const i64 row = frow[slot];
+        if (row < 0)
             return;
-        const i64 row = fidx ? fidx[fg] : fg;
         const int hsel = slot & 1, pair = slot >> 1;
 #if LDPC_PACKED
         constexpr int NB8 = (N + 7) / 8;
@@ -204,12 +234,23 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
             for (int n = tid; n < N; n += LDPC_THREADS)
                 post[row * N + n] = (short)(float)Lh[2 * (PAD + n * FWP + pair) + hsel];
 #else
-        for (int n = tid; n < N; n += LDPC_THREADS) {
-            const float v = (float)Lh[2 * (PAD + n * FWP + pair) + hsel];
-            bits[row * N + n] = v > 0.0f ? 0 : 1;
-            if (post)
-                post[row * N + n] = (short)v;
+        // wide, N a multiple of 4 and the caller's buffer 4-byte aligned: a
+        // thread writes four bits as one 32-bit word
+        if (wide && N % 4 == 0 && ((unsigned long long)bits & 3) == 0) {
+            for (int b = tid; b < N / 4; b += LDPC_THREADS) {
+                u32 w = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    w |= ((float)Lh[2 * (PAD + (4 * b + q) * FWP + pair) + hsel] > 0.0f ? 0u : 1u) << (8 * q);
+                *(u32 *)(bits + row * N + 4 * b) = w;
+            }
+        } else {
+            for (int n = tid; n < N; n += LDPC_THREADS)
+                bits[row * N + n] = (float)Lh[2 * (PAD + n * FWP + pair) + hsel] > 0.0f ? 0 : 1;
         }
+        if (post)
+            for (int n = tid; n < N; n += LDPC_THREADS)
+                post[row * N + n] = (short)(float)Lh[2 * (PAD + n * FWP + pair) + hsel];
 #endif
     };
 
@@ -382,7 +423,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
             // halves are not written back later)
             for (int slot = 0; slot < FW; ++slot)
                 if (conv[slot] == 1)
-                    write_frame(slot);
+                    write_frame(slot, false);
             __syncthreads();
             if (tid < FW && conv[tid] == 1)
                 conv[tid] = 2;
@@ -405,5 +446,5 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
     }
     for (int slot = 0; slot < FW; ++slot)
         if (conv[slot] == 0)
-            write_frame(slot);
+            write_frame(slot, true);
 }
