@@ -180,6 +180,36 @@ __device__ __forceinline__ void fwd_layer(int i, int t, int r, int rb, float *Ls
         aux = idx2 | (par << 5);
 }
 
+// The transmitted codeword's bits at variables j*Z + r (j < NB) of frame f,
+// bit j of the result, read once per kernel instead of once per iteration
+// (codes of up to 32 block columns; wider codes read them when used).
+__device__ __forceinline__ u32 target_bits(const u8 *__restrict__ cw, i64 f, int r, bool on)
+{
+    u32 b = 0;
+    if constexpr (NB <= 32) {
+        if (on) {
+            u8 c[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                c[j] = cw[f * N + j * Z + r];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                b |= (c[j] ? 1u : 0u) << j;
+        }
+    }
+    return b;
+}
+
+// BPSK symbol of the transmitted bit at variable j*Z + r of frame f: -1 for
+// bit 1, +1 for bit 0.
+__device__ __forceinline__ float target_sign(const u8 *__restrict__ cw, u32 bits, i64 f, int j, int r)
+{
+    if constexpr (NB <= 32)
+        return (bits >> j) & 1u ? -1.0f : 1.0f;
+    else
+        return cw[f * N + j * Z + r] ? -1.0f : 1.0f;
+}
+
 extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
     const float *__restrict__ llr, const u8 *__restrict__ cw, const i64 F, const int T, const float *__restrict__ w,
     float *__restrict__ ckpt, float *__restrict__ loss_tf, float *__restrict__ post)
@@ -192,13 +222,30 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
     const i64 f = (i64)blockIdx.x * G + g;
     const bool on = g < G && f < F;
     const int rb = r * FWP + g;
-    for (int s = 0; s < G; ++s) {
-        const i64 fs = (i64)blockIdx.x * G + s;
-        if (fs >= F)
-            break;
-        for (int n = tid; n < N; n += LDPC_THREADS)
-            Ls[n * FWP + s] = llr[fs * N + n] + 0.0f;
+    // channel values: the workgroup's frames are one flat range of G*N
+    // values, all of a thread's loads in flight before the first is waited
+    // for (a value past F is read from frame 0 of the workgroup, which
+    // exists, and dropped)
+    {
+        const i64 fb = (i64)blockIdx.x * G;
+        const i64 nval = (F - fb < G ? F - fb : G) * (i64)N;
+        constexpr int PER = (G * N + LDPC_THREADS - 1) / LDPC_THREADS;
+        float v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = j * LDPC_THREADS + tid;
+            v[j] = llr[fb * N + (k < nval ? k : 0)];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = j * LDPC_THREADS + tid;
+            if (k < nval) {
+                const int s = k / N, n = k - s * N;
+                Ls[n * FWP + s] = v[j] + 0.0f;
+            }
+        }
     }
+    const u32 xbits = target_bits(cw, f, r, on);
     float sm1[MB], sm2[MB];
     u32 ssg[MB];
 #pragma unroll
@@ -236,7 +283,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void ldpc_nms_fwd(
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int n = j * Z + r;
-                const float x = cw[f * N + n] ? -1.0f : 1.0f;
+                const float x = target_sign(cw, xbits, f, j, r);
                 acc += softplus(-x * Ls[n * FWP + g]);
             }
         }
@@ -297,6 +344,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_wave
     const bool on = g < G && f < F;
     const int rb = r * FWP + g;
     const double inv = 1.0 / ((double)T * (double)F * (double)N);
+    const u32 xbits = target_bits(cw, f, r, on);
     float gR[ED];   // d loss / d R_e of the iteration being reversed
 #pragma unroll
     for (int k = 0; k < ED; ++k)
@@ -336,7 +384,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) __attribute__((amdgpu_wave
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int n = j * Z + r;
-                const float x = cw[f * N + n] ? -1.0f : 1.0f;
+                const float x = target_sign(cw, xbits, f, j, r);
                 gL[n * FWP + g] += -x * sigmoid(-x * Ls[n * FWP + g]) * sc;
             }
         }
