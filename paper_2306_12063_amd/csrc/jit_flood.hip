@@ -138,20 +138,35 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
     const int rb = r * FWP + slot0;
     const i64 f0 = (i64)blockIdx.x * FW;
 
-    // channel values into both arrays (-0.0 -> +0.0 as in jit_decode.hip)
-    for (int slot = 0; slot < FW; ++slot) {
-        const i64 fg = f0 + slot;
-        if (fg >= F)
-            break;
-        const TIn *p = llr + fg * (i64)N;
-        for (int n = tid; n < N; n += LDPC_THREADS) {
+    // channel values into both arrays (-0.0 -> +0.0 as in jit_decode.hip):
+    // the workgroup's frames are one flat range, up to 16 loads per thread in
+    // flight before the first is waited for (a value past F is read from the
+    // workgroup's first frame, which exists, and dropped)
+    {
+        const i64 nval = (F - f0 < FW ? F - f0 : (i64)FW) * (i64)N;
+        constexpr int PER = (FW * N + LDPC_THREADS - 1) / LDPC_THREADS;
+        constexpr int CH = PER < 16 ? PER : 16;
+        for (int j0 = 0; j0 < PER; j0 += CH) {
+            TIn x[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int k = (j0 + j) * LDPC_THREADS + tid;
+                x[j] = llr[f0 * N + (k < nval ? k : 0)];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int k = (j0 + j) * LDPC_THREADS + tid;
+                if (k < nval) {
+                    const int slot = k / N, n = k - slot * N;
 #if LDPC_PATH == 0
-            const float v = p[n] + 0.0f;
+                    const float v = x[j] + 0.0f;
 #else
-            const float v = (float)p[n];
+                    const float v = (float)x[j];
 #endif
-            Ls[PAD + n * FWP + slot] = v;
-            Ls[ZOFF + PAD + n * FWP + slot] = v;
+                    Ls[PAD + n * FWP + slot] = v;
+                    Ls[ZOFF + PAD + n * FWP + slot] = v;
+                }
+            }
         }
     }
     if (tid < FW)

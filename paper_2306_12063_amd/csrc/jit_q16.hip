@@ -85,13 +85,30 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) void LDPC_KERNEL(
     const int slot0 = g * KF;
     const int rb = r * FWP + slot0;
     const i64 f0 = (i64)blockIdx.x * FW;
-    for (int slot = 0; slot < FW; ++slot) {
-        const i64 fg = f0 + slot;
-        if (fg >= F)
-            break;
-        const short *p = llr + fg * (i64)N;
-        for (int n = tid; n < N; n += LDPC_THREADS)
-            Ls[PAD + n * FWP + slot] = (int)p[n];
+    // channel values: the workgroup's frames are one flat range, up to 16
+    // loads per thread in flight before the first is waited for (a value
+    // past F is read from the workgroup's first frame, which exists, and
+    // dropped)
+    {
+        const i64 nval = (F - f0 < FW ? F - f0 : (i64)FW) * (i64)N;
+        constexpr int PER = (FW * N + LDPC_THREADS - 1) / LDPC_THREADS;
+        constexpr int CH = PER < 16 ? PER : 16;
+        for (int j0 = 0; j0 < PER; j0 += CH) {
+            short x[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int k = (j0 + j) * LDPC_THREADS + tid;
+                x[j] = llr[f0 * N + (k < nval ? k : 0)];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int k = (j0 + j) * LDPC_THREADS + tid;
+                if (k < nval) {
+                    const int slot = k / N, n = k - slot * N;
+                    Ls[PAD + n * FWP + slot] = (int)x[j];
+                }
+            }
+        }
     }
     if (tid < FW)
         unsat[tid] = 0;
