@@ -147,6 +147,37 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
     // values; each thread puts up to 16 loads in flight before it waits for
     // the first, so a workgroup pays one or two round trips to HBM before its
     // first layer, not one per frame and pass.
+#if LDPC_MODE == 2
+    // weight table: the weights of iterations t (buffer t & 1) and t + 1 in
+    // LDS; row i's weights at i*WROW + e as a 16-bit pair (the same weight
+    // for both frames), 16-byte aligned rows read as broadcast loads of four.
+    // The next iteration's weights are loaded into registers at its
+    // predecessor's first layer (fetch) and stored to LDS at its last layer
+    // (put), so the round trip to HBM overlaps the layers; the loads are
+    // unconditional (an entry without an edge reads element 0, not stored).
+    constexpr int WROW = (MAXD + 3) / 4 * 4;
+    __shared__ __attribute__((aligned(16))) u32 Wst[2][MB * WROW];
+    constexpr int NWT = (MB * WROW + LDPC_THREADS - 1) / LDPC_THREADS;
+    u32 wreg[NWT];
+    bool wok[NWT];
+    auto fetch_weights = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < NWT; ++j) {
+            const int k = tid + j * LDPC_THREADS;
+            const bool in = k < MB * WROW;
+            const int i = in ? k / WROW : 0, e = in ? k - i * WROW : 0;
+            wok[j] = in && e < kDeg[i];
+            wreg[j] = wt[wok[j] ? (i64)t * (MB * NB) + i * NB + kCol[i][e] : 0];
+        }
+    };
+    auto put_weights = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < NWT; ++j)
+            if (wok[j])
+                Wst[t & 1][tid + j * LDPC_THREADS] = wreg[j] | (wreg[j] << 16);
+    };
+    fetch_weights(0);   // its round trip overlaps the channel values'
+#endif
     __shared__ i64 frow[FW];   // row of each frame slot's buffers, -1 past F
     __shared__ int conv[FW];
     if (tid < FW) {
@@ -193,22 +224,7 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
     const u32 beta = W((h2){(_Float16)(float)offset, (_Float16)(float)offset});
     const float wqf = (float)wq;
 #if LDPC_MODE == 2
-    // weight table: the weights of iterations t (buffer t & 1) and t + 1 in
-    // LDS, copied one iteration ahead; row i's weights at i*WROW + e as a
-    // 16-bit pair (the same weight for both frames), 16-byte aligned rows
-    // read as broadcast loads of four
-    constexpr int WROW = (MAXD + 3) / 4 * 4;
-    __shared__ __attribute__((aligned(16))) u32 Wst[2][MB * WROW];
-    auto stage_weights = [&](int t) {
-        for (int k = tid; k < MB * WROW; k += LDPC_THREADS) {
-            const int i = k / WROW, e = k - i * WROW;
-            if (e < kDeg[i]) {
-                const u32 w = wt[(i64)t * (MB * NB) + i * NB + kCol[i][e]];
-                Wst[t & 1][k] = w | (w << 16);
-            }
-        }
-    };
-    stage_weights(0);
+    put_weights(0);
 #endif
     __syncthreads();
 
@@ -263,11 +279,11 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
             constexpr int d = kDeg[i];
             constexpr int eo = edge_off(i);
 #if LDPC_MODE == 2
-            // the next iteration's weights, after this layer's barrier (the
-            // buffer was last read in iteration t - 1)
+            // the next iteration's weights: loads issued here, stored to
+            // their buffer (last read in iteration t - 1) at the last layer
             if constexpr (i == 0)
                 if (t + 1 < max_iter)
-                    stage_weights(t + 1);
+                    fetch_weights(t + 1);
 #endif
             int rr = r;
             if constexpr (i >= LDPC_HOIST)
@@ -366,6 +382,11 @@ extern "C" __global__ __launch_bounds__(LDPC_THREADS) LDPC_OCCUPANCY void LDPC_K
                 if (i == MB - 1)
                     lastbad = (d & 1 ? bad ^ hw : bad) & 0x80008000u;
             }
+#if LDPC_MODE == 2
+            if constexpr (i == MB - 1)
+                if (t + 1 < max_iter)
+                    put_weights(t + 1);
+#endif
             __syncthreads();
         });
         if (check) {
