@@ -25,7 +25,8 @@ def test_roofline_entry_takes_the_larger_fraction():
     assert r["bound"] == "lds" and r["unit"] == "GB/s" and abs(r["frac"] - 0.3) < 1e-9
     # a packed 16-bit kernel is priced at twice the 32-bit VALU issue rate
     assert r["valu"]["peak"] == round(2 * bench.PEAK_VALU_TOPS, 1)
-    # the survey's per-frame LDS model: T (2 b_L E + 2 b_row M)
+    # per-frame LDS model of the method: each edge's posterior read and
+    # written per iteration, each row's state read and written: T (2 b_L E + 2 b_row M)
     assert bench.lds_model_bytes("f32", 100, 10, 10) == 10 * (2 * 4 * 100 + 2 * 16 * 10)
     assert bench.lds_model_bytes("i8", 100, 10, 10) == 10 * (2 * 2 * 100 + 2 * 8 * 10)
 
